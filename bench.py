@@ -1,0 +1,216 @@
+"""Benchmark of the fused lattice ES-BGK step on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): 2-D
+force-driven Poiseuille flow with thermal walls, 1024 x 1024 cells, D2Q37
+(Hermite order 4), periodic in x, diffuse walls in y at T = 1.0 / 1.05,
+g_x = 1e-5 in lattice units, Kn = 0.05, Pr = 2/3, populations stored as FP32
+deviations and collided in FP32. One "step" is one launch of the fused pull +
+collide kernel over all cells, with the populations resident in HBM.
+
+Printed: one JSON line with MLUPS (the metric), the roofline of the step
+kernel (algorithmic bytes 2 Q s per cell update / measured kernel time
+against the 8 TB/s HBM peak), the same workload with plain FP64 and with
+FP16 storage, the batched-channel workload in one persistent launch against
+a per-problem FP64 loop, and the FP64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--only-main]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_lattice(cfg, storage):
+    from paper_1209_6548_amd import Lattice
+    dims = tuple(cfg["dims"]) + (1,) * (3 - len(cfg["dims"]))
+    lat = Lattice(cfg["velset"], dims[0], dims[1], dims[2], walls=cfg["walls"], storage=storage)
+    lat.set_gas(cfg["Kn"], cfg["Pr"], cfg["varpi"])
+    if cfg["walls"]:
+        lat.set_wall(0, cfg["T_w"][0], cfg["u_w"][0])
+        lat.set_wall(1, cfg["T_w"][1], cfg["u_w"][1])
+    lat.set_body_force(cfg["g"])
+    lat.init_equilibrium()
+    return lat
+
+
+def time_steps(lat, steps, warmup):
+    """Average step time (ms) from HIP events on the stream the kernels run on
+    (torch's current stream, which the binding hands to the library)."""
+    import torch
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    lat.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_single(cfg, storage, steps, warmup):
+    lat = make_lattice(cfg, storage)
+    ms = time_steps(lat, steps, warmup)
+    cells = int(np.prod(cfg["dims"]))
+    s = {"f64": 8, "f32": 4, "f16": 2}[storage]
+    bytes_per_step = 2 * lat.Q * s * cells
+    out = dict(storage=storage, ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6,
+               algorithmic_GBs=bytes_per_step / (ms * 1e-3) / 1e9, bytes_per_cell=2 * lat.Q * s)
+    red = lat.reduce()
+    out["finite"] = bool(np.isfinite(red["mass"]) and np.isfinite(red["energy"]))
+    lat.close()
+    return out
+
+
+def bench_batch(r, steps, warmup, fp64_sample=16):
+    """Batched channels in one persistent launch vs. the same channels stepped
+    one problem at a time with the FP64 single-lattice path."""
+    import torch
+
+    from paper_1209_6548_amd import Batch, make_problem, workloads
+    specs = workloads.channel_batch(r)
+    probs = [make_problem("D2Q37", s["dims"][0], s["dims"][1], storage="f32", Kn=s["Kn"], Pr=s["Pr"],
+                          T_w=s["T_w"], u_w=s["u_w"], g=s["g"]) for s in specs]
+    cells = sum(s["dims"][0] * s["dims"][1] for s in specs)
+    b = Batch(probs)
+    layout = b.autotune(20)
+    b.init_equilibrium()
+    b.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    out = dict(problems=len(specs), cells=cells, layout=dict(threads=layout[0], bins=layout[1]),
+               ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6)
+    b.close()
+    # per-problem FP64 loop on a sample of the same problems (same per-step work)
+    rng = np.random.default_rng(0)
+    pick = rng.choice(len(specs), fp64_sample, replace=False)
+    lats = []
+    for i in pick:
+        s = specs[i]
+        cfg = dict(s, dims=s["dims"])
+        lats.append(make_lattice(cfg, "f64"))
+    n = max(10, steps // 10)
+    for L in lats:
+        L.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        for L in lats:
+            L.step(1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    c_s = sum(specs[i]["dims"][0] * specs[i]["dims"][1] for i in pick)
+    out["per_problem_fp64"] = dict(sample_problems=int(fp64_sample), mlups=c_s * n / dt / 1e6)
+    for L in lats:
+        L.close()
+    return out
+
+
+def cpu_baseline(r, budget_s=20.0):
+    """The FP64 oracle on a bounded sample of the same workload: the 1024 x
+    1024 channel's per-cell work (D2Q37, walls, force, N = 4) on a 256 x 256
+    instance with the same Kn, Pr and walls, stepped until the time budget."""
+    from oracle import lattice as OL
+    from oracle import quadrature
+    from paper_1209_6548_amd import workloads
+    cfg = workloads.poiseuille_thermal_1024(r, n=256)
+    vs = quadrature.d2q37()
+    prob = OL.Problem(vs, cfg["dims"], Kn=cfg["Kn"], Pr=cfg["Pr"], varpi=cfg["varpi"], walls=True,
+                      wall_lo=OL.Wall(cfg["T_w"][0]), wall_hi=OL.Wall(cfg["T_w"][1]), g=cfg["g"])
+    M = prob.M
+    f = OL.equilibrium_state(prob, np.ones(M), np.zeros((M, 2)), np.ones(M))
+    f = OL.step(f, prob)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < budget_s and n < 200:
+        f = OL.step(f, prob)
+        n += 1
+    dt = time.perf_counter() - t0
+    threads = 1
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
+    except Exception:
+        pass
+    return dict(value=M * n / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
+                sample=f"256x256 D2Q37 channel (same Kn, Pr, walls, force as the 1024x1024 case), {n} steps, "
+                       f"{dt:.1f} s; cores = BLAS threads available to numpy")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only-main", action="store_true", help="time only the headline FP32 run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1209_6548_amd import lattice_info, workloads
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    r = lattice_info("D2Q37")["r"]
+    cfg = workloads.poiseuille_thermal_1024(r, storage="f32")
+    log(f"headline: {cfg['name']} f32, {args.steps} steps after {args.warmup} warmup")
+    main_run = bench_single(cfg, "f32", args.steps, args.warmup)
+    log(f"f32: {main_run['mlups']:.0f} MLUPS, {main_run['algorithmic_GBs']:.0f} GB/s")
+    variants = {}
+    if not args.only_main:
+        for st in ("f64", "f16"):
+            variants[st] = bench_single(cfg, st, max(20, args.steps // 2), args.warmup)
+            log(f"{st}: {variants[st]['mlups']:.0f} MLUPS, {variants[st]['algorithmic_GBs']:.0f} GB/s")
+        variants["batched_channels"] = bench_batch(r, max(50, args.steps), args.warmup)
+        log(f"batch: {variants['batched_channels']['mlups']:.0f} MLUPS")
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(r)
+        log(f"cpu: {cpu['value']:.3f} MLUPS")
+    ms = main_run["ms_per_step"]
+    achieved = main_run["algorithmic_GBs"]
+    line = {
+        "metric": "MLUPS", "value": round(main_run["mlups"], 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "velset": "D2Q37", "order_N": 4, "cells": 1024 * 1024,
+                   "storage": "f32 deviational", "Kn": cfg["Kn"], "Pr": cfg["Pr"], "walls_T": list(cfg["T_w"]),
+                   "g_x_nondim": cfg["g"][0], "scheme": "trapezoid"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_step<D2Q37, float>", "bytes_per_cell": main_run["bytes_per_cell"]},
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

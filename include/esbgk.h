@@ -1,0 +1,218 @@
+/*
+ * esbgk.h - C ABI of the MI355X lattice ES-BGK library (libesbgk.so).
+ *
+ * The library advances the lattice ES-BGK model of Meng, Zhang,
+ * Hadjiconstantinou, Radtke and Shan ("Lattice ellipsoidal statistical BGK
+ * model for thermal non-equilibrium flows", arXiv 1209.6548) on one gfx950
+ * GPU: one fused pull-stream + collide kernel per time step.
+ *
+ * Units are the paper's nondimensional ones (Sec. 2.2): lengths in L (the
+ * reference length of Kn), velocities in sqrt(R T0), temperature in T0,
+ * density in rho0, body force g = L g^ / (R T0). One cell is dx = 1/N_L,
+ * one step is dt = dx / r (every population moves by its integer lattice
+ * vector e_alpha; c_alpha = r e_alpha).
+ *
+ * Populations. The model's discrete distribution f_alpha (eq. lbgk) is kept
+ * as the deviation h_alpha = f_alpha / w_alpha - 1 in FP64, FP32 or FP16, in
+ * structure-of-arrays order [alpha][z][y][x] (x fastest). Population I/O at
+ * this boundary is always FP64 h in that order. Velocity order: index 0 is
+ * rest, 1..P the vectors whose first non-zero component is positive sorted by
+ * |e|^2 then by descending tuple order, alpha + P holds -e_alpha
+ * (esbgk_lattice_info returns the table). The stored state is the
+ * post-collision population of the last step; the moments of a state are
+ * those of the distribution it streams into (the current time level).
+ *
+ * Conventions.
+ *  - Every call returns an int status: ESBGK_OK (0) or a negative code.
+ *    Nothing throws or aborts across the ABI.
+ *  - Arguments are validated on the host before anything is launched; an
+ *    invalid call changes nothing and returns ESBGK_E_INVALID.
+ *  - Device memory is owned by the caller: esbgk_workspace_bytes tells how
+ *    much, esbgk_create binds it. The library never frees it. The handle owns
+ *    only host memory and HIP graph objects.
+ *  - All work is queued on the HIP stream given at creation. Calls that
+ *    return data to host memory (read_moments, get_populations, get_state,
+ *    reduce, last_reduction) synchronise that stream; the others are
+ *    asynchronous.
+ *  - A HIP failure makes the handle sticky: every later call returns the same
+ *    code until esbgk_destroy. esbgk_last_error describes it.
+ *  - A handle is not thread-safe. Handles on different streams are
+ *    independent.
+ */
+#ifndef ESBGK_H
+#define ESBGK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ESBGK_OK = 0,
+  ESBGK_E_INVALID = -1,   /* argument out of range or inconsistent */
+  ESBGK_E_NOMEM = -2,     /* workspace smaller than esbgk_workspace_bytes */
+  ESBGK_E_HIP = -3,       /* a HIP runtime call failed (sticky) */
+  ESBGK_E_NONFINITE = -4, /* a reduction met a non-finite value, rho <= 0 or T <= 0 (sticky) */
+  ESBGK_E_UNSTABLE = -5,  /* Euler step with dt/tau or dt/(Pr tau) >= 2 at rho = T = 1 */
+  ESBGK_E_STATE = -6      /* call out of order (e.g. step before the state is set) */
+};
+
+enum { ESBGK_D2Q37 = 1, ESBGK_D3Q39 = 2 };            /* velocity set */
+enum { ESBGK_F64 = 0, ESBGK_F32 = 1, ESBGK_F16 = 2 };  /* storage of h; FP64 computes in FP64, the others in FP32 */
+enum { ESBGK_TRAPEZOID = 0, ESBGK_EULER = 1 };         /* time discretisation of eq. lbgk */
+
+typedef struct esbgk_ctx esbgk_ctx;
+typedef struct esbgk_batch esbgk_batch;
+
+/* Geometry and numerics of one lattice.
+ *  velset  ESBGK_D2Q37 (2-D, Hermite order N = 4) or ESBGK_D3Q39 (3-D, N = 3)
+ *  nx,ny,nz  cells per axis; nz must be 1 for D2Q37. nx*ny*nz < 2^31.
+ *  walls   0: periodic in every axis. 1: diffuse walls (Sec. 3.2) half a cell
+ *          outside the first and last layer of the last axis (y in 2-D, z in
+ *          3-D); that axis needs at least 6 cells. Other axes are periodic.
+ *  storage ESBGK_F64 / ESBGK_F32 / ESBGK_F16.
+ *  scheme  ESBGK_TRAPEZOID (second order) or ESBGK_EULER (forward Euler along
+ *          the characteristic, the paper's Sec. 3.1 update at Courant 1).
+ *  n_ref   N_L, the number of cells across the reference length L of Kn;
+ *          0 means the extent of the wall axis (walls = 1) or nx. */
+typedef struct {
+  int velset, nx, ny, nz, walls, storage, scheme, n_ref;
+} esbgk_shape;
+
+/* Velocity set of Sec. 2.2 (abscissae c = r e and weights of a Gauss-Hermite
+ * quadrature, eq. weight for the 1-D case), derived on the host by matching
+ * the moments of the Gaussian weight function. Any output pointer may be
+ * NULL. e receives Q*D ints (row per velocity), w receives Q doubles. Touches
+ * no GPU. */
+int esbgk_lattice_info(int velset, int* Q, int* D, int* N, double* r, int* e, double* w);
+
+/* Bytes of device workspace a lattice of this shape needs (0 if the shape is
+ * invalid). The caller allocates it (e.g. torch.empty(n, dtype=uint8)),
+ * 256-byte aligned. */
+size_t esbgk_workspace_bytes(const esbgk_shape* shape);
+
+/* Bind a workspace and a HIP stream (hipStream_t, NULL = default stream) to a
+ * new handle. The workspace must stay allocated until esbgk_destroy.
+ * Gas defaults: Kn = 0.1, Pr = 1, varpi = 0.5; walls at rest at T = 1; g = 0.
+ * Errors: E_INVALID (shape), E_NOMEM (ws_bytes too small), E_HIP. */
+int esbgk_create(const esbgk_shape* shape, void* d_workspace, size_t ws_bytes,
+                 void* hip_stream, esbgk_ctx** out);
+
+/* Release the handle (never the caller's workspace or stream). */
+int esbgk_destroy(esbgk_ctx* ctx);
+
+/* Gas parameters (Sec. 2.1-2.2): Kn = mu0 sqrt(R T0)/(p0 L); Pr = 1/(1-b)
+ * with -1/2 <= b <= 1, i.e. Pr >= 2/3; viscosity law mu/mu0 = (T/T0)^varpi,
+ * varpi in [0.5, 1]. tau = (Kn/Pr) mu / p per cell. Errors: E_INVALID,
+ * E_UNSTABLE (Euler only). */
+int esbgk_set_gas(esbgk_ctx* ctx, double Kn, double Pr, double varpi);
+
+/* Diffuse wall state (Sec. 3.2, full accommodation): side 0 = low wall,
+ * 1 = high wall; temperature T_w > 0 and velocity u_w[3] (its wall-normal
+ * component must be 0). Populations leaving the wall are rho_W S(T_w, u_w),
+ * eq. feq0 at the bulk order N, with rho_W from the flux balance of Sec. 3.2.
+ * E_INVALID if the lattice has no walls. */
+int esbgk_set_wall(esbgk_ctx* ctx, int side, double T_w, const double u_w[3]);
+
+/* Body force g[3] (eq. esbgk, its Hermite expansion in Sec. 2.2). */
+int esbgk_set_body_force(esbgk_ctx* ctx, const double g[3]);
+
+/* Initial state f_alpha = rho S_alpha(T, u) (1 + amplitude * noise_alpha)
+ * per cell, S of eq. feq0 at the bulk order N. rho, T: [cells] host FP64;
+ * u: [D][cells]; noise: [Q][cells]. NULL fields mean rho = 1, u = 0, T = 1;
+ * NULL noise means none. Resets the step counter. */
+int esbgk_init_equilibrium(esbgk_ctx* ctx, const double* rho, const double* u,
+                           const double* T, const double* noise, double amplitude);
+
+/* Set / read the stored populations as FP64 h[Q][cells] (host memory).
+ * set rounds to the storage type (round to nearest even). */
+int esbgk_set_populations(esbgk_ctx* ctx, const double* h);
+int esbgk_get_populations(esbgk_ctx* ctx, double* h);
+
+/* Raw state (storage bytes of the populations + the step counter) for
+ * checkpoint / restart; esbgk_state_bytes gives the size. Restoring and
+ * stepping is bit-identical to never having saved. */
+size_t esbgk_state_bytes(const esbgk_ctx* ctx);
+int esbgk_get_state(esbgk_ctx* ctx, void* h_raw, size_t nbytes);
+int esbgk_set_state(esbgk_ctx* ctx, const void* h_raw, size_t nbytes);
+
+/* Advance n >= 0 time steps (asynchronous). Each step streams every
+ * population along e_alpha (pull, periodic wrap, wall re-emission) and
+ * collides: fbar* = fbar - omega (fbar - f_ES^N) + phi dt F, with f_ES^N the
+ * Hermite projection of the anisotropic Gaussian (eq. approxfeq, lambda of
+ * eq. cfeq) and F the force expansion of Sec. 2.2. Every R steps
+ * (esbgk_set_reduce_interval) the step also forms the FP64 reductions. */
+int esbgk_step(esbgk_ctx* ctx, int64_t n);
+
+/* Macroscopic fields of eq. mac at the current level, FP64 [F][cells] host:
+ * rho, u[D], T, sigma (trace-free, components xx,xy,yy or
+ * xx,xy,xz,yy,yz,zz), q[D]. F = 9 (2-D) or 14 (3-D); *F receives it. */
+int esbgk_read_moments(esbgk_ctx* ctx, double* h_out, int* F);
+
+/* FP64 reductions of the current level (out[8]): total mass sum rho,
+ * energy sum 1/2 sum_alpha f c^2, momentum sum rho u (3), mass flow rate
+ * through a plane normal to x, dx^(D-1)/nx sum rho u_x, the relative change
+ * ||u - u_prev||_2/||u||_2 since the previous reduction (0 for the first),
+ * and the step count. Computed in a fixed order (deterministic). Returns
+ * E_NONFINITE (sticky) if a cell has a non-finite value, rho <= 0 or
+ * T <= 0. */
+int esbgk_reduce(esbgk_ctx* ctx, double out[8]);
+
+/* R > 0: fuse the reductions into every R-th step (R = 0 disables);
+ * esbgk_last_reduction returns the latest such result. */
+int esbgk_set_reduce_interval(esbgk_ctx* ctx, int64_t R);
+int esbgk_last_reduction(esbgk_ctx* ctx, double out[8]);
+
+/* Steps taken since the state was last set. */
+int64_t esbgk_steps_done(const esbgk_ctx* ctx);
+
+/* Text of the last error on this handle ("" if none). */
+const char* esbgk_last_error(const esbgk_ctx* ctx);
+
+/* ---- Batches of independent channels -----------------------------------
+ * Many small channel problems (all D2Q37 or all D3Q39, same storage and
+ * scheme, walls across the last axis, any extents) advance together in one
+ * persistent kernel launch: each workgroup owns whole problems and loops over
+ * the steps with workgroup barriers in between. */
+typedef struct {
+  esbgk_shape shape;          /* velset/storage/scheme must match the batch */
+  double Kn, Pr, varpi;
+  double T_w[2], u_w[2][3];   /* low / high wall */
+  double g[3];
+} esbgk_problem;
+
+size_t esbgk_batch_workspace_bytes(const esbgk_problem* problems, int n);
+int esbgk_batch_create(const esbgk_problem* problems, int n, void* d_workspace,
+                       size_t ws_bytes, void* hip_stream, esbgk_batch** out);
+int esbgk_batch_destroy(esbgk_batch* b);
+/* Uniform rest state at rho = 1, T = 1 (optionally times 1 + amplitude*noise;
+ * noise holds Q * (sum of all cells) values, problem after problem, each
+ * [Q][cells]). */
+int esbgk_batch_init_equilibrium(esbgk_batch* b, const double* noise, double amplitude);
+/* Advance every problem n steps in one persistent launch (asynchronous). */
+int esbgk_batch_step(esbgk_batch* b, int64_t n);
+/* Fields of problem i (same layout as esbgk_read_moments); synchronises. */
+int esbgk_batch_read_moments(esbgk_batch* b, int i, double* h_out, int* F);
+/* Stored populations of problem i as FP64 h[Q][cells_i]; synchronises. */
+int esbgk_batch_get_populations(esbgk_batch* b, int i, double* h);
+/* Launch layout: workgroup size (multiple of 64, at most 1024 for F32, 512
+ * for F16, 256 for F64 storage) and number of bins (one workgroup each;
+ * problems are packed longest first into the lightest bin). The default is
+ * the largest workgroup and one bin per resident workgroup. */
+int esbgk_batch_set_layout(esbgk_batch* b, int threads, int nbins);
+int esbgk_batch_layout(const esbgk_batch* b, int* threads, int* nbins);
+/* Autotuner: time steps_per_trial steps of every candidate layout
+ * (workgroups of 256..max threads x 1, 2, 4, 8 bins per compute unit) on the
+ * uniform rest state and keep the fastest. Overwrites the state: call
+ * esbgk_batch_init_equilibrium afterwards. */
+int esbgk_batch_autotune(esbgk_batch* b, int steps_per_trial);
+int64_t esbgk_batch_steps_done(const esbgk_batch* b);
+const char* esbgk_batch_last_error(const esbgk_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESBGK_H */

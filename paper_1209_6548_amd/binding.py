@@ -1,0 +1,349 @@
+"""Thin Python binding of libesbgk.so (argument marshalling only).
+
+Every step of the lattice ES-BGK path runs in the library's HIP kernels.
+PyTorch only provides the device workspace (torch.empty, uint8) and the HIP
+stream (torch.cuda.current_stream). Calls mirror the C ABI in
+include/esbgk.h; a non-zero status raises EsbgkError with the library's
+message.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libesbgk.so")
+
+OK, E_INVALID, E_NOMEM, E_HIP, E_NONFINITE, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5, -6
+D2Q37, D3Q39 = 1, 2
+F64, F32, F16 = 0, 1, 2
+TRAPEZOID, EULER = 0, 1
+
+_VELSET = {"D2Q37": D2Q37, "D3Q39": D3Q39}
+_STORAGE = {"f64": F64, "f32": F32, "f16": F16}
+_SCHEME = {"trapezoid": TRAPEZOID, "euler": EULER}
+_NAMES = {E_INVALID: "E_INVALID", E_NOMEM: "E_NOMEM", E_HIP: "E_HIP", E_NONFINITE: "E_NONFINITE",
+          E_UNSTABLE: "E_UNSTABLE", E_STATE: "E_STATE"}
+
+
+class EsbgkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int) for n in ("velset", "nx", "ny", "nz", "walls", "storage", "scheme", "n_ref")]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("shape", Shape), ("Kn", ctypes.c_double), ("Pr", ctypes.c_double), ("varpi", ctypes.c_double),
+                ("T_w", ctypes.c_double * 2), ("u_w", (ctypes.c_double * 3) * 2), ("g", ctypes.c_double * 3)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1209_6548_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, D, SZ, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_int64
+        DP = ctypes.POINTER(ctypes.c_double)
+        sig = {
+            "esbgk_lattice_info": (I, [I, P, P, P, P, P, P]),
+            "esbgk_workspace_bytes": (SZ, [P]),
+            "esbgk_create": (I, [P, P, SZ, P, P]),
+            "esbgk_destroy": (I, [P]),
+            "esbgk_set_gas": (I, [P, D, D, D]),
+            "esbgk_set_wall": (I, [P, I, D, DP]),
+            "esbgk_set_body_force": (I, [P, DP]),
+            "esbgk_init_equilibrium": (I, [P, DP, DP, DP, DP, D]),
+            "esbgk_set_populations": (I, [P, DP]),
+            "esbgk_get_populations": (I, [P, DP]),
+            "esbgk_state_bytes": (SZ, [P]),
+            "esbgk_get_state": (I, [P, P, SZ]),
+            "esbgk_set_state": (I, [P, P, SZ]),
+            "esbgk_step": (I, [P, I64]),
+            "esbgk_read_moments": (I, [P, DP, P]),
+            "esbgk_reduce": (I, [P, DP]),
+            "esbgk_set_reduce_interval": (I, [P, I64]),
+            "esbgk_last_reduction": (I, [P, DP]),
+            "esbgk_steps_done": (I64, [P]),
+            "esbgk_last_error": (ctypes.c_char_p, [P]),
+            "esbgk_batch_workspace_bytes": (SZ, [P, I]),
+            "esbgk_batch_create": (I, [P, I, P, SZ, P, P]),
+            "esbgk_batch_destroy": (I, [P]),
+            "esbgk_batch_init_equilibrium": (I, [P, DP, D]),
+            "esbgk_batch_step": (I, [P, I64]),
+            "esbgk_batch_read_moments": (I, [P, I, DP, P]),
+            "esbgk_batch_get_populations": (I, [P, I, DP]),
+            "esbgk_batch_set_layout": (I, [P, I, I]),
+            "esbgk_batch_layout": (I, [P, P, P]),
+            "esbgk_batch_autotune": (I, [P, I]),
+            "esbgk_batch_steps_done": (I64, [P]),
+            "esbgk_batch_last_error": (ctypes.c_char_p, [P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, shape=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def lattice_info(velset):
+    """Velocity set (Sec. 2.2) as derived by the library: Q, D, N, r, e, w."""
+    vid = _VELSET[velset] if isinstance(velset, str) else velset
+    Q, D, N = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    r = ctypes.c_double()
+    e = (ctypes.c_int * (39 * 3))()
+    w = (ctypes.c_double * 39)()
+    rc = lib().esbgk_lattice_info(vid, ctypes.byref(Q), ctypes.byref(D), ctypes.byref(N), ctypes.byref(r), e, w)
+    if rc:
+        raise EsbgkError(rc, "lattice_info")
+    q, d = Q.value, D.value
+    return dict(Q=q, D=d, N=N.value, r=r.value, e=np.array(e[:q * d], dtype=np.int64).reshape(q, d),
+                w=np.array(w[:q]))
+
+
+def _stream_ptr(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def split_fields(raw, D):
+    """Name the rows of a moments array [F][cells]."""
+    k = 0
+    out = {"rho": raw[0]}
+    k = 1
+    out["u"] = raw[k:k + D]
+    k += D
+    out["T"] = raw[k]
+    k += 1
+    ns = D * (D + 1) // 2
+    out["sigma"] = raw[k:k + ns]
+    k += ns
+    out["q"] = raw[k:k + D]
+    return out
+
+
+class Lattice:
+    """One lattice on the GPU: a handle of the C ABI plus its workspace."""
+
+    def __init__(self, velset="D2Q37", nx=64, ny=64, nz=1, walls=False, storage="f32", scheme="trapezoid",
+                 n_ref=0, device="cuda:0"):
+        import torch
+        self.device = torch.device(device)
+        self.velset = velset
+        info = lattice_info(velset)
+        self.Q, self.D, self.N, self.r = info["Q"], info["D"], info["N"], info["r"]
+        self.dims = (nx, ny) if self.D == 2 else (nx, ny, nz)
+        self.cells = nx * ny * nz
+        self.storage = storage
+        self.shape = Shape(_VELSET[velset], nx, ny, nz, int(bool(walls)), _STORAGE[storage], _SCHEME[scheme], n_ref)
+        L = lib()
+        nbytes = L.esbgk_workspace_bytes(ctypes.byref(self.shape))
+        if nbytes == 0:
+            raise EsbgkError(E_INVALID, "invalid shape")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._ctx = ctypes.c_void_p()
+        rc = L.esbgk_create(ctypes.byref(self.shape), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                            _stream_ptr(self.device), ctypes.byref(self._ctx))
+        if rc:
+            raise EsbgkError(rc, "create")
+
+    # -- plumbing --
+    def _check(self, rc, what):
+        if rc:
+            msg = lib().esbgk_last_error(self._ctx)
+            raise EsbgkError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            lib().esbgk_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- parameters --
+    def set_gas(self, Kn, Pr, varpi=0.5):
+        self._check(lib().esbgk_set_gas(self._ctx, Kn, Pr, varpi), "set_gas")
+
+    def set_wall(self, side, T, u=(0.0, 0.0, 0.0)):
+        uu = np.zeros(3)
+        uu[:len(u)] = u
+        self._check(lib().esbgk_set_wall(self._ctx, int(side), float(T), _dp(uu)), "set_wall")
+
+    def set_body_force(self, g):
+        gg = np.zeros(3)
+        gg[:len(g)] = g
+        self._check(lib().esbgk_set_body_force(self._ctx, _dp(gg)), "set_body_force")
+
+    # -- state --
+    def init_equilibrium(self, rho=None, u=None, T=None, noise=None, amplitude=0.0):
+        rho = _f64(rho, (self.cells,))
+        u = _f64(u, (self.D, self.cells))
+        T = _f64(T, (self.cells,))
+        noise = _f64(noise, (self.Q, self.cells))
+        self._check(lib().esbgk_init_equilibrium(self._ctx, _dp(rho), _dp(u), _dp(T), _dp(noise), float(amplitude)),
+                    "init_equilibrium")
+
+    def set_populations(self, h):
+        h = _f64(h, (self.Q, self.cells))
+        self._check(lib().esbgk_set_populations(self._ctx, _dp(h)), "set_populations")
+
+    def get_populations(self):
+        h = np.empty((self.Q, self.cells))
+        self._check(lib().esbgk_get_populations(self._ctx, _dp(h)), "get_populations")
+        return h
+
+    def get_state(self):
+        n = lib().esbgk_state_bytes(self._ctx)
+        buf = (ctypes.c_char * n)()
+        self._check(lib().esbgk_get_state(self._ctx, buf, n), "get_state")
+        return bytes(buf)
+
+    def set_state(self, raw):
+        buf = ctypes.create_string_buffer(raw, len(raw))
+        self._check(lib().esbgk_set_state(self._ctx, buf, len(raw)), "set_state")
+
+    def step(self, n=1):
+        self._check(lib().esbgk_step(self._ctx, int(n)), "step")
+
+    @property
+    def steps_done(self):
+        return lib().esbgk_steps_done(self._ctx)
+
+    def read_moments_raw(self):
+        F = 9 if self.D == 2 else 14
+        out = np.empty((F, self.cells))
+        f = ctypes.c_int()
+        self._check(lib().esbgk_read_moments(self._ctx, _dp(out), ctypes.byref(f)), "read_moments")
+        return out
+
+    def read_moments(self):
+        return split_fields(self.read_moments_raw(), self.D)
+
+    def _red(self, out):
+        return dict(mass=out[0], energy=out[1], mom=out[2:5].copy(), mdot=out[5], residual=out[6], step=int(out[7]))
+
+    def reduce(self):
+        out = np.empty(8)
+        self._check(lib().esbgk_reduce(self._ctx, _dp(out)), "reduce")
+        return self._red(out)
+
+    def set_reduce_interval(self, R):
+        self._check(lib().esbgk_set_reduce_interval(self._ctx, int(R)), "set_reduce_interval")
+
+    def last_reduction(self):
+        out = np.empty(8)
+        self._check(lib().esbgk_last_reduction(self._ctx, _dp(out)), "last_reduction")
+        return self._red(out)
+
+
+def make_problem(velset, nx, ny, nz=1, storage="f32", scheme="trapezoid", n_ref=0, Kn=0.1, Pr=1.0, varpi=0.5,
+                 T_w=(1.0, 1.0), u_w=((0, 0, 0), (0, 0, 0)), g=(0, 0, 0)):
+    p = Problem()
+    p.shape = Shape(_VELSET[velset], nx, ny, nz, 1, _STORAGE[storage], _SCHEME[scheme], n_ref)
+    p.Kn, p.Pr, p.varpi = Kn, Pr, varpi
+    for s in range(2):
+        p.T_w[s] = T_w[s]
+        for i in range(3):
+            p.u_w[s][i] = u_w[s][i] if i < len(u_w[s]) else 0.0
+    for i in range(3):
+        p.g[i] = g[i] if i < len(g) else 0.0
+    return p
+
+
+class Batch:
+    """Many independent channels advanced by one persistent kernel."""
+
+    def __init__(self, problems, device="cuda:0"):
+        import torch
+        self.device = torch.device(device)
+        self.n = len(problems)
+        arr = (Problem * self.n)(*problems)
+        self._arr = arr
+        vs = problems[0].shape.velset
+        info = lattice_info(vs)
+        self.Q, self.D = info["Q"], info["D"]
+        self.cells = [p.shape.nx * p.shape.ny * p.shape.nz for p in problems]
+        L = lib()
+        nbytes = L.esbgk_batch_workspace_bytes(arr, self.n)
+        if nbytes == 0:
+            raise EsbgkError(E_INVALID, "invalid batch")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._b = ctypes.c_void_p()
+        rc = L.esbgk_batch_create(arr, self.n, ctypes.c_void_p(self.ws.data_ptr()), nbytes, _stream_ptr(self.device),
+                                  ctypes.byref(self._b))
+        if rc:
+            raise EsbgkError(rc, "batch_create")
+
+    def _check(self, rc, what):
+        if rc:
+            msg = lib().esbgk_batch_last_error(self._b)
+            raise EsbgkError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            lib().esbgk_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_equilibrium(self, noise=None, amplitude=0.0):
+        noise = _f64(noise, (-1,))
+        self._check(lib().esbgk_batch_init_equilibrium(self._b, _dp(noise), float(amplitude)), "batch_init")
+
+    def autotune(self, steps_per_trial=20):
+        self._check(lib().esbgk_batch_autotune(self._b, int(steps_per_trial)), "batch_autotune")
+        return self.layout()
+
+    def set_layout(self, threads, nbins):
+        self._check(lib().esbgk_batch_set_layout(self._b, int(threads), int(nbins)), "batch_set_layout")
+
+    def layout(self):
+        t, n = ctypes.c_int(), ctypes.c_int()
+        self._check(lib().esbgk_batch_layout(self._b, ctypes.byref(t), ctypes.byref(n)), "batch_layout")
+        return t.value, n.value
+
+    def step(self, n=1):
+        self._check(lib().esbgk_batch_step(self._b, int(n)), "batch_step")
+
+    def read_moments(self, i):
+        F = 9 if self.D == 2 else 14
+        out = np.empty((F, self.cells[i]))
+        f = ctypes.c_int()
+        self._check(lib().esbgk_batch_read_moments(self._b, int(i), _dp(out), ctypes.byref(f)), "batch_moments")
+        return split_fields(out, self.D)
+
+    def get_populations(self, i):
+        h = np.empty((self.Q, self.cells[i]))
+        self._check(lib().esbgk_batch_get_populations(self._b, int(i), _dp(h)), "batch_populations")
+        return h

@@ -1,0 +1,561 @@
+// C ABI of the lattice ES-BGK library: handle management, validation,
+// workspace layout, parameter upload, state I/O and the step driver.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/esbgk.h"
+#include "kernels.h"
+#include "tables.h"
+
+using namespace esbgk;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr uint32_t BLOCK = 256;
+constexpr uint32_t STAGE_CELLS = 65536;   // cells per staged host transfer
+
+size_t align_up(size_t n) { return (n + ALIGN - 1) / ALIGN * ALIGN; }
+
+size_t storage_size(int storage) { return storage == ESBGK_F64 ? 8 : (storage == ESBGK_F32 ? 4 : 2); }
+size_t compute_size(int storage) { return storage == ESBGK_F64 ? 8 : 4; }
+
+// Workspace layout; every region 256-byte aligned.
+struct Layout {
+  size_t pop[2], wp[2], lc, pp, lc64, pp64, uprev, red_part, red_out, staging, total;
+  size_t staging_bytes;
+};
+
+bool valid_shape(const esbgk_shape* s, std::string* why) {
+  auto fail = [&](const char* m) { if (why) *why = m; return false; };
+  if (!s) return fail("null shape");
+  if (s->velset != ESBGK_D2Q37 && s->velset != ESBGK_D3Q39) return fail("velset must be ESBGK_D2Q37 or ESBGK_D3Q39");
+  if (s->nx < 1 || s->ny < 1 || s->nz < 1) return fail("extents must be >= 1");
+  if (s->velset == ESBGK_D2Q37 && s->nz != 1) return fail("D2Q37 needs nz = 1");
+  const uint64_t n = uint64_t(s->nx) * uint64_t(s->ny) * uint64_t(s->nz);
+  if (n >= (uint64_t(1) << 31)) return fail("nx*ny*nz must be < 2^31");
+  if (s->walls != 0 && s->walls != 1) return fail("walls must be 0 or 1");
+  if (s->walls) {
+    const int nw = s->velset == ESBGK_D2Q37 ? s->ny : s->nz;
+    if (nw < 6) return fail("the wall axis needs at least 6 cells");
+  }
+  if (s->storage < ESBGK_F64 || s->storage > ESBGK_F16) return fail("storage must be F64, F32 or F16");
+  if (s->scheme != ESBGK_TRAPEZOID && s->scheme != ESBGK_EULER) return fail("scheme must be TRAPEZOID or EULER");
+  if (s->n_ref < 0) return fail("n_ref must be >= 0");
+  return true;
+}
+
+int ncols_of(const esbgk_shape* s) {
+  return s->velset == ESBGK_D2Q37 ? s->nx : s->nx * s->ny;
+}
+
+Layout layout_of(const esbgk_shape* s) {
+  const HostLattice* lat = host_lattice(s->velset);
+  Layout L{};
+  const size_t cells = size_t(s->nx) * s->ny * s->nz;
+  const size_t ss = storage_size(s->storage), cs = compute_size(s->storage);
+  const size_t Q = size_t(lat->Q), D = size_t(lat->D);
+  const size_t ncols = size_t(ncols_of(s));
+  const size_t nblocks = (cells + BLOCK - 1) / BLOCK;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
+  L.pop[0] = take(Q * cells * ss);
+  L.pop[1] = take(Q * cells * ss);
+  L.wp[0] = take(6 * ncols * cs);
+  L.wp[1] = take(6 * ncols * cs);
+  L.lc = take(cs == 8 ? sizeof(LatConsts<double>) : sizeof(LatConsts<float>));
+  L.pp = take(cs == 8 ? sizeof(ProbParams<double>) : sizeof(ProbParams<float>));
+  // FP64 blocks for the read-out kernels (the same blocks when storage is FP64)
+  L.lc64 = cs == 8 ? L.lc : take(sizeof(LatConsts<double>));
+  L.pp64 = cs == 8 ? L.pp : take(sizeof(ProbParams<double>));
+  L.uprev = take(D * cells * cs);
+  L.red_part = take(nblocks * NRED * sizeof(double));
+  L.red_out = take(NRED * sizeof(double));
+  const size_t stage_cells = std::min<size_t>(cells, STAGE_CELLS);
+  const size_t per_cell = std::max<size_t>(nfields(int(D)), 2 + D + Q) * sizeof(double);
+  L.staging_bytes = stage_cells * per_cell;
+  L.staging = take(L.staging_bytes);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct esbgk_ctx {
+  esbgk_shape shape{};
+  const HostLattice* lat = nullptr;
+  Geometry geo{};
+  Layout lay{};
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int cur = 0;                    // buffer holding the current state
+  bool state_set = false;
+  int64_t steps = 0;
+  int64_t R = 0;                  // fused reduction interval
+  int have_prev = 0;
+  int64_t last_red_step = -1;
+  int sticky = 0;
+  std::string err;
+  // gas, walls, force
+  double Kn = 0.1, Pr = 1.0, varpi = 0.5;
+  double Tw[2] = {1.0, 1.0};
+  double uw[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  double g[3] = {0, 0, 0};
+  int n_ref = 0;
+  // host copies of the device parameter blocks
+  ProbParams<double> pp64{};
+  ProbParams<float> pp32{};
+  LatConsts<double> lc64{};
+  LatConsts<float> lc32{};
+
+  char* at(size_t off) const { return ws + off; }
+  bool f64() const { return shape.storage == ESBGK_F64; }
+};
+
+namespace {
+
+int set_err(esbgk_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(esbgk_ctx* c, hipError_t e, const char* where) {
+  c->sticky = ESBGK_E_HIP;
+  c->err = std::string(where) + ": " + hipGetErrorString(e);
+  return ESBGK_E_HIP;
+}
+
+#define HIP_OR_FAIL(ctx, expr, where)            \
+  do {                                           \
+    hipError_t _e = (expr);                      \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, where); \
+  } while (0)
+
+StepArgs base_args(const esbgk_ctx* c) {
+  StepArgs a{};
+  a.geo = c->geo;
+  a.src = c->at(c->lay.pop[c->cur]);
+  a.dst = c->at(c->lay.pop[1 - c->cur]);
+  a.wp_src = c->at(c->lay.wp[c->cur]);
+  a.wp_dst = c->at(c->lay.wp[1 - c->cur]);
+  a.lc = c->at(c->lay.lc);
+  a.pp = c->at(c->lay.pp);
+  a.lc64 = c->at(c->lay.lc64);
+  a.pp64 = c->at(c->lay.pp64);
+  a.uprev = c->at(c->lay.uprev);
+  a.have_prev = c->have_prev;
+  a.reduce = 0;
+  a.red_part = reinterpret_cast<double*>(c->at(c->lay.red_part));
+  a.stream = c->stream;
+  return a;
+}
+
+int upload_params(esbgk_ctx* c) {
+  const HostProblem hp = make_problem(*c->lat, c->n_ref, c->shape.scheme, c->Kn, c->Pr, c->varpi, c->g, c->Tw, c->uw);
+  pack_params<double>(hp, c->lat->Q, c->pp64);
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->at(c->lay.pp64), &c->pp64, sizeof(c->pp64), hipMemcpyHostToDevice, c->stream),
+              "upload parameters");
+  if (!c->f64()) {
+    pack_params<float>(hp, c->lat->Q, c->pp32);
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->at(c->lay.pp), &c->pp32, sizeof(c->pp32), hipMemcpyHostToDevice, c->stream),
+                "upload parameters");
+  }
+  // host-side copies must outlive the asynchronous copy
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "upload parameters");
+  return ESBGK_OK;
+}
+
+int check_stable(const esbgk_ctx* c, double Kn, double Pr) {
+  if (c->shape.scheme != ESBGK_EULER) return ESBGK_OK;
+  const double dt = 1.0 / (double(c->n_ref) * c->lat->r);
+  const double x = dt * Pr / Kn, y = dt / Kn;   // dt/tau and dt/(Pr tau) at rho = T = 1
+  return (x < 2.0 && y < 2.0) ? ESBGK_OK : ESBGK_E_UNSTABLE;
+}
+
+int refresh_partials(esbgk_ctx* c) {
+  if (!c->shape.walls) return ESBGK_OK;
+  StepArgs a = base_args(c);
+  a.wp_dst = c->at(c->lay.wp[c->cur]);
+  HIP_OR_FAIL(c, launch_wall_partials(c->shape.velset, c->shape.storage, a), "wall partial sums");
+  return ESBGK_OK;
+}
+
+int fetch_reduction(esbgk_ctx* c, double out[8], int64_t step) {
+  double raw[NRED];
+  HIP_OR_FAIL(c, hipMemcpyAsync(raw, c->at(c->lay.red_out), sizeof(raw), hipMemcpyDeviceToHost, c->stream),
+              "read reduction");
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "read reduction");
+  const int D = c->lat->D;
+  const double dx = 1.0 / double(c->n_ref);
+  out[0] = raw[0];
+  out[1] = raw[1];
+  out[2] = raw[2];
+  out[3] = raw[3];
+  out[4] = raw[4];
+  out[5] = std::pow(dx, D - 1) / double(c->shape.nx) * raw[2];
+  out[6] = raw[6] > 0.0 ? std::sqrt(raw[5] / raw[6]) : 0.0;
+  out[7] = double(step);
+  if (raw[7] != 0.0 || !std::isfinite(raw[0]) || !std::isfinite(raw[1])) {
+    c->sticky = ESBGK_E_NONFINITE;
+    c->err = "reduction found a non-finite value, rho <= 0 or T <= 0";
+    return ESBGK_E_NONFINITE;
+  }
+  return ESBGK_OK;
+}
+
+#define CHECK_CTX(c)                         \
+  do {                                       \
+    if (!(c)) return ESBGK_E_INVALID;        \
+    if ((c)->sticky) return (c)->sticky;     \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int esbgk_lattice_info(int velset, int* Q, int* D, int* N, double* r, int* e, double* w) {
+  const HostLattice* lat = host_lattice(velset);
+  if (!lat) return ESBGK_E_INVALID;
+  if (Q) *Q = lat->Q;
+  if (D) *D = lat->D;
+  if (N) *N = lat->N;
+  if (r) *r = lat->r;
+  if (e)
+    for (int a = 0; a < lat->Q; ++a)
+      for (int i = 0; i < lat->D; ++i) e[a * lat->D + i] = lat->e[size_t(a) * 3 + i];
+  if (w)
+    for (int a = 0; a < lat->Q; ++a) w[a] = lat->w[a];
+  return ESBGK_OK;
+}
+
+size_t esbgk_workspace_bytes(const esbgk_shape* shape) {
+  if (!valid_shape(shape, nullptr) || !host_lattice(shape->velset)) return 0;
+  return layout_of(shape).total;
+}
+
+int esbgk_create(const esbgk_shape* shape, void* d_workspace, size_t ws_bytes, void* hip_stream, esbgk_ctx** out) {
+  if (!out) return ESBGK_E_INVALID;
+  *out = nullptr;
+  std::string why;
+  if (!valid_shape(shape, &why)) return ESBGK_E_INVALID;
+  const HostLattice* lat = host_lattice(shape->velset);
+  if (!lat) return ESBGK_E_INVALID;
+  const Layout lay = layout_of(shape);
+  if (!d_workspace || ws_bytes < lay.total) return ESBGK_E_NOMEM;
+  if (reinterpret_cast<uintptr_t>(d_workspace) % ALIGN) return ESBGK_E_INVALID;
+  esbgk_ctx* c = new esbgk_ctx();
+  c->shape = *shape;
+  c->lat = lat;
+  c->lay = lay;
+  c->ws = static_cast<char*>(d_workspace);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->n_ref = shape->n_ref > 0 ? shape->n_ref : (shape->walls ? (lat->D == 2 ? shape->ny : shape->nz) : shape->nx);
+  Geometry& g = c->geo;
+  g.nx = uint32_t(shape->nx);
+  g.ny = uint32_t(shape->ny);
+  g.nz = uint32_t(shape->nz);
+  g.ncells = g.nx * g.ny * g.nz;
+  g.ncols = uint32_t(ncols_of(shape));
+  g.walls = uint32_t(shape->walls);
+  g.nxy = g.nx * g.ny;
+  g.div_nx = make_fastdiv(g.nx);
+  g.div_ny = make_fastdiv(g.ny);
+  pack_lattice<double>(*lat, c->lc64);
+  int rc = hipMemcpyAsync(c->at(lay.lc64), &c->lc64, sizeof(c->lc64), hipMemcpyHostToDevice, c->stream) == hipSuccess
+               ? ESBGK_OK : ESBGK_E_HIP;
+  if (rc == ESBGK_OK && !c->f64()) {
+    pack_lattice<float>(*lat, c->lc32);
+    rc = hipMemcpyAsync(c->at(lay.lc), &c->lc32, sizeof(c->lc32), hipMemcpyHostToDevice, c->stream) == hipSuccess
+             ? ESBGK_OK : ESBGK_E_HIP;
+  }
+  if (rc == ESBGK_OK) rc = upload_params(c);
+  // wall partial sums start at zero (a state must be set before stepping)
+  if (rc == ESBGK_OK &&
+      hipMemsetAsync(c->at(lay.wp[0]), 0, lay.wp[1] - lay.wp[0], c->stream) != hipSuccess) rc = ESBGK_E_HIP;
+  if (rc == ESBGK_OK &&
+      hipMemsetAsync(c->at(lay.wp[1]), 0, lay.wp[1] - lay.wp[0], c->stream) != hipSuccess) rc = ESBGK_E_HIP;
+  if (rc == ESBGK_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = ESBGK_E_HIP;
+  if (rc != ESBGK_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return ESBGK_OK;
+}
+
+int esbgk_destroy(esbgk_ctx* ctx) {
+  if (!ctx) return ESBGK_E_INVALID;
+  delete ctx;
+  return ESBGK_OK;
+}
+
+int esbgk_set_gas(esbgk_ctx* c, double Kn, double Pr, double varpi) {
+  CHECK_CTX(c);
+  if (!(Kn > 0.0) || !std::isfinite(Kn)) return set_err(c, ESBGK_E_INVALID, "Kn must be > 0");
+  if (!(Pr >= 2.0 / 3.0 - 1e-12) || !std::isfinite(Pr))
+    return set_err(c, ESBGK_E_INVALID, "Pr must be >= 2/3 (b = 1 - 1/Pr >= -1/2)");
+  if (!(varpi >= 0.5 && varpi <= 1.0)) return set_err(c, ESBGK_E_INVALID, "varpi must be in [0.5, 1]");
+  if (check_stable(c, Kn, Pr) != ESBGK_OK)
+    return set_err(c, ESBGK_E_UNSTABLE, "Euler step unstable: dt/tau or dt/(Pr tau) >= 2");
+  c->Kn = Kn;
+  c->Pr = Pr;
+  c->varpi = varpi;
+  return upload_params(c);
+}
+
+int esbgk_set_wall(esbgk_ctx* c, int side, double T_w, const double u_w[3]) {
+  CHECK_CTX(c);
+  if (!c->shape.walls) return set_err(c, ESBGK_E_INVALID, "lattice has no walls");
+  if (side != 0 && side != 1) return set_err(c, ESBGK_E_INVALID, "side must be 0 or 1");
+  if (!(T_w > 0.0) || !std::isfinite(T_w)) return set_err(c, ESBGK_E_INVALID, "T_w must be > 0");
+  if (!u_w) return set_err(c, ESBGK_E_INVALID, "u_w is null");
+  const int W = c->lat->D - 1;
+  if (u_w[W] != 0.0) return set_err(c, ESBGK_E_INVALID, "wall velocity must be tangential");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(u_w[i])) return set_err(c, ESBGK_E_INVALID, "u_w must be finite");
+  c->Tw[side] = T_w;
+  for (int i = 0; i < 3; ++i) c->uw[side][i] = i < c->lat->D ? u_w[i] : 0.0;
+  return upload_params(c);
+}
+
+int esbgk_set_body_force(esbgk_ctx* c, const double g[3]) {
+  CHECK_CTX(c);
+  if (!g) return set_err(c, ESBGK_E_INVALID, "g is null");
+  for (int i = 0; i < 3; ++i) {
+    if (!std::isfinite(g[i])) return set_err(c, ESBGK_E_INVALID, "g must be finite");
+    c->g[i] = i < c->lat->D ? g[i] : 0.0;
+  }
+  return upload_params(c);
+}
+
+int esbgk_init_equilibrium(esbgk_ctx* c, const double* rho, const double* u, const double* T, const double* noise,
+                           double amplitude) {
+  CHECK_CTX(c);
+  if (noise && !std::isfinite(amplitude)) return set_err(c, ESBGK_E_INVALID, "amplitude must be finite");
+  const uint32_t cells = c->geo.ncells;
+  const int D = c->lat->D, Q = c->lat->Q;
+  StepArgs a = base_args(c);
+  a.dst = c->at(c->lay.pop[c->cur]);
+  const bool staged = rho || u || T || noise;
+  if (!staged) {
+    HIP_OR_FAIL(c, launch_init(c->shape.velset, c->shape.storage, a, c->lat->r, nullptr, nullptr, nullptr, nullptr,
+                               0.0, 0, cells),
+                "init");
+  } else {
+    double* st = reinterpret_cast<double*>(c->at(c->lay.staging));
+    for (uint32_t c0 = 0; c0 < cells; c0 += STAGE_CELLS) {
+      const uint32_t n = std::min(STAGE_CELLS, cells - c0);
+      double* d_rho = st;
+      double* d_u = d_rho + n;
+      double* d_T = d_u + size_t(D) * n;
+      double* d_noise = d_T + n;
+      if (rho) HIP_OR_FAIL(c, hipMemcpyAsync(d_rho, rho + c0, n * 8, hipMemcpyHostToDevice, c->stream), "stage");
+      if (u)
+        for (int d = 0; d < D; ++d)
+          HIP_OR_FAIL(c, hipMemcpyAsync(d_u + size_t(d) * n, u + size_t(d) * cells + c0, n * 8,
+                                        hipMemcpyHostToDevice, c->stream), "stage");
+      if (T) HIP_OR_FAIL(c, hipMemcpyAsync(d_T, T + c0, n * 8, hipMemcpyHostToDevice, c->stream), "stage");
+      if (noise)
+        for (int q = 0; q < Q; ++q)
+          HIP_OR_FAIL(c, hipMemcpyAsync(d_noise + size_t(q) * n, noise + size_t(q) * cells + c0, n * 8,
+                                        hipMemcpyHostToDevice, c->stream), "stage");
+      HIP_OR_FAIL(c, launch_init(c->shape.velset, c->shape.storage, a, c->lat->r, rho ? d_rho : nullptr,
+                                 u ? d_u : nullptr, T ? d_T : nullptr, noise ? d_noise : nullptr, amplitude, c0, n),
+                  "init");
+      HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "init");
+    }
+  }
+  int rc = refresh_partials(c);
+  if (rc) return rc;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "init");
+  c->state_set = true;
+  c->steps = 0;
+  c->have_prev = 0;
+  c->last_red_step = -1;
+  return ESBGK_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename S>
+void narrow_plane(const double* in, size_t n, std::vector<unsigned char>& out) {
+  out.resize(n * sizeof(S));
+  S* o = reinterpret_cast<S*>(out.data());
+  for (size_t i = 0; i < n; ++i) o[i] = S(in[i]);
+}
+
+template <typename S>
+void widen_plane(const unsigned char* in, size_t n, double* out) {
+  const S* s = reinterpret_cast<const S*>(in);
+  for (size_t i = 0; i < n; ++i) out[i] = double(s[i]);
+}
+
+}  // namespace
+
+extern "C" {
+
+int esbgk_set_populations(esbgk_ctx* c, const double* h) {
+  CHECK_CTX(c);
+  if (!h) return set_err(c, ESBGK_E_INVALID, "h is null");
+  const size_t cells = c->geo.ncells, ss = storage_size(c->shape.storage);
+  char* dst = c->at(c->lay.pop[c->cur]);
+  std::vector<unsigned char> buf;
+  for (int q = 0; q < c->lat->Q; ++q) {
+    const double* src = h + size_t(q) * cells;
+    if (c->shape.storage == ESBGK_F64) {
+      HIP_OR_FAIL(c, hipMemcpyAsync(dst + size_t(q) * cells * ss, src, cells * ss, hipMemcpyHostToDevice, c->stream),
+                  "set populations");
+      HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "set populations");
+      continue;
+    }
+    if (c->shape.storage == ESBGK_F32) narrow_plane<float>(src, cells, buf);
+    else narrow_plane<_Float16>(src, cells, buf);
+    HIP_OR_FAIL(c, hipMemcpyAsync(dst + size_t(q) * cells * ss, buf.data(), cells * ss, hipMemcpyHostToDevice,
+                                  c->stream), "set populations");
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "set populations");
+  }
+  int rc = refresh_partials(c);
+  if (rc) return rc;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "set populations");
+  c->state_set = true;
+  c->steps = 0;
+  c->have_prev = 0;
+  c->last_red_step = -1;
+  return ESBGK_OK;
+}
+
+int esbgk_get_populations(esbgk_ctx* c, double* h) {
+  CHECK_CTX(c);
+  if (!h) return set_err(c, ESBGK_E_INVALID, "h is null");
+  if (!c->state_set) return set_err(c, ESBGK_E_STATE, "no state set");
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "get populations");
+  const size_t cells = c->geo.ncells, ss = storage_size(c->shape.storage);
+  const char* src = c->at(c->lay.pop[c->cur]);
+  std::vector<unsigned char> buf(cells * ss);
+  for (int q = 0; q < c->lat->Q; ++q) {
+    HIP_OR_FAIL(c, hipMemcpyAsync(buf.data(), src + size_t(q) * cells * ss, cells * ss, hipMemcpyDeviceToHost,
+                                  c->stream), "get populations");
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "get populations");
+    double* o = h + size_t(q) * cells;
+    if (c->shape.storage == ESBGK_F64) widen_plane<double>(buf.data(), cells, o);
+    else if (c->shape.storage == ESBGK_F32) widen_plane<float>(buf.data(), cells, o);
+    else widen_plane<_Float16>(buf.data(), cells, o);
+  }
+  return ESBGK_OK;
+}
+
+size_t esbgk_state_bytes(const esbgk_ctx* c) {
+  if (!c) return 0;
+  return size_t(c->lat->Q) * c->geo.ncells * storage_size(c->shape.storage) + sizeof(int64_t);
+}
+
+int esbgk_get_state(esbgk_ctx* c, void* h_raw, size_t nbytes) {
+  CHECK_CTX(c);
+  if (!h_raw || nbytes != esbgk_state_bytes(c)) return set_err(c, ESBGK_E_INVALID, "state buffer size mismatch");
+  if (!c->state_set) return set_err(c, ESBGK_E_STATE, "no state set");
+  const size_t pop = nbytes - sizeof(int64_t);
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "get state");
+  HIP_OR_FAIL(c, hipMemcpyAsync(h_raw, c->at(c->lay.pop[c->cur]), pop, hipMemcpyDeviceToHost, c->stream), "get state");
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "get state");
+  std::memcpy(static_cast<char*>(h_raw) + pop, &c->steps, sizeof(int64_t));
+  return ESBGK_OK;
+}
+
+int esbgk_set_state(esbgk_ctx* c, const void* h_raw, size_t nbytes) {
+  CHECK_CTX(c);
+  if (!h_raw || nbytes != esbgk_state_bytes(c)) return set_err(c, ESBGK_E_INVALID, "state buffer size mismatch");
+  const size_t pop = nbytes - sizeof(int64_t);
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "set state");
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->at(c->lay.pop[c->cur]), h_raw, pop, hipMemcpyHostToDevice, c->stream), "set state");
+  int rc = refresh_partials(c);
+  if (rc) return rc;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "set state");
+  std::memcpy(&c->steps, static_cast<const char*>(h_raw) + pop, sizeof(int64_t));
+  c->state_set = true;
+  c->have_prev = 0;
+  return ESBGK_OK;
+}
+
+int esbgk_step(esbgk_ctx* c, int64_t n) {
+  CHECK_CTX(c);
+  if (n < 0) return set_err(c, ESBGK_E_INVALID, "n must be >= 0");
+  if (!c->state_set) return set_err(c, ESBGK_E_STATE, "no state set");
+  const uint32_t nblocks = (c->geo.ncells + BLOCK - 1) / BLOCK;
+  for (int64_t i = 0; i < n; ++i) {
+    StepArgs a = base_args(c);
+    const bool red = c->R > 0 && ((c->steps + 1) % c->R == 0);
+    a.reduce = red ? 1 : 0;
+    HIP_OR_FAIL(c, launch_step(c->shape.velset, c->shape.storage, a), "step");
+    if (red) {
+      HIP_OR_FAIL(c, launch_reduce_finalize(a.red_part, nblocks, reinterpret_cast<double*>(c->at(c->lay.red_out)),
+                                            c->stream), "reduce");
+      c->have_prev = 1;
+      c->last_red_step = c->steps;
+    }
+    c->cur ^= 1;
+    c->steps += 1;
+  }
+  return ESBGK_OK;
+}
+
+int esbgk_read_moments(esbgk_ctx* c, double* h_out, int* F) {
+  CHECK_CTX(c);
+  if (!h_out) return set_err(c, ESBGK_E_INVALID, "h_out is null");
+  if (!c->state_set) return set_err(c, ESBGK_E_STATE, "no state set");
+  const int nf = nfields(c->lat->D);
+  if (F) *F = nf;
+  const uint32_t cells = c->geo.ncells;
+  double* st = reinterpret_cast<double*>(c->at(c->lay.staging));
+  std::vector<double> tmp;
+  StepArgs a = base_args(c);
+  for (uint32_t c0 = 0; c0 < cells; c0 += STAGE_CELLS) {
+    const uint32_t n = std::min(STAGE_CELLS, cells - c0);
+    HIP_OR_FAIL(c, launch_moments(c->shape.velset, c->shape.storage, a, c0, n, st), "moments");
+    tmp.resize(size_t(nf) * n);
+    HIP_OR_FAIL(c, hipMemcpyAsync(tmp.data(), st, tmp.size() * 8, hipMemcpyDeviceToHost, c->stream), "moments");
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "moments");
+    for (int f = 0; f < nf; ++f) std::memcpy(h_out + size_t(f) * cells + c0, tmp.data() + size_t(f) * n, n * 8);
+  }
+  return ESBGK_OK;
+}
+
+int esbgk_reduce(esbgk_ctx* c, double out[8]) {
+  CHECK_CTX(c);
+  if (!out) return set_err(c, ESBGK_E_INVALID, "out is null");
+  if (!c->state_set) return set_err(c, ESBGK_E_STATE, "no state set");
+  const uint32_t nblocks = (c->geo.ncells + BLOCK - 1) / BLOCK;
+  StepArgs a = base_args(c);
+  HIP_OR_FAIL(c, launch_reduce(c->shape.velset, c->shape.storage, a), "reduce");
+  HIP_OR_FAIL(c, launch_reduce_finalize(a.red_part, nblocks, reinterpret_cast<double*>(c->at(c->lay.red_out)),
+                                        c->stream), "reduce");
+  c->have_prev = 1;
+  c->last_red_step = c->steps;
+  return fetch_reduction(c, out, c->steps);
+}
+
+int esbgk_set_reduce_interval(esbgk_ctx* c, int64_t R) {
+  CHECK_CTX(c);
+  if (R < 0) return set_err(c, ESBGK_E_INVALID, "R must be >= 0");
+  c->R = R;
+  return ESBGK_OK;
+}
+
+int esbgk_last_reduction(esbgk_ctx* c, double out[8]) {
+  CHECK_CTX(c);
+  if (!out) return set_err(c, ESBGK_E_INVALID, "out is null");
+  if (c->last_red_step < 0) return set_err(c, ESBGK_E_STATE, "no reduction has run");
+  return fetch_reduction(c, out, c->last_red_step);
+}
+
+int64_t esbgk_steps_done(const esbgk_ctx* c) { return c ? c->steps : -1; }
+
+const char* esbgk_last_error(const esbgk_ctx* c) { return c ? c->err.c_str() : "null handle"; }
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Persistent kernel for batches of independent channel problems.
+//
+// The host packs the problems into bins of roughly equal cell count (longest
+// problem first, each into the currently lightest bin); one workgroup owns one
+// bin for the whole launch. Within a step every thread takes cells of the bin
+// in turn (cell -> problem through a prefix table in LDS), pulls, collides
+// and stores exactly as the single-lattice kernel does, with the problem's
+// own geometry and parameter block; a workgroup barrier separates steps, so
+// the bin advances n steps in one launch with no host round trip. The
+// barrier's workgroup-scope release/acquire makes the global-memory writes of
+// one step visible to every wave of the workgroup in the next.
+
+#include <hip/hip_runtime.h>
+
+#include "batch.h"
+#include "stream.h"
+
+namespace esbgk {
+
+template <class L, typename S, typename C>
+__device__ __forceinline__ void batch_cell(const BatchProblem& bp, uint32_t cell, const S* __restrict__ srcb,
+                                           S* __restrict__ dstb, const C* __restrict__ wpsb, C* __restrict__ wpdb,
+                                           const LatConsts<C>* __restrict__ lc,
+                                           const ProbParams<C>* __restrict__ pp) {
+  const Geometry& geo = bp.geo;
+  const S* src = srcb + bp.pop_off;
+  S* dst = dstb + bp.pop_off;
+  const C* wps = wpsb + bp.wp_off;
+  C* wpd = wpdb + bp.wp_off;
+  const CellPos p = cell_pos(cell, geo);
+  C h[L::Q];
+  gather<L, S, C, C>(h, src, geo, cell, p, wps, pp, false);
+  CellState<L, C> st;
+  collide<L, C>(h, lc, pp, st);
+#pragma unroll
+  for (int a = 0; a < L::Q; ++a) dst[size_t(a) * geo.ncells + cell] = narrow<S, C>(h[a]);
+  write_wall_partials<L, S, C>([&](int a) { return narrow<S, C>(h[a]); }, p, geo, lc, wpd);
+}
+
+template <class L, typename S, typename C, int MAXT>
+__global__ void __launch_bounds__(MAXT)
+k_batch(const BatchProblem* __restrict__ probs, const ProbParams<C>* __restrict__ pps,
+        const uint32_t* __restrict__ bin_first, const uint32_t* __restrict__ order, S* __restrict__ bufA,
+        S* __restrict__ bufB, C* __restrict__ wpA, C* __restrict__ wpB, const LatConsts<C>* __restrict__ lc,
+        int64_t nsteps, int parity) {
+  __shared__ uint32_t cum[BATCH_MAX_PER_BIN + 1];
+  __shared__ uint32_t pid[BATCH_MAX_PER_BIN];
+  const uint32_t p0 = bin_first[blockIdx.x], p1 = bin_first[blockIdx.x + 1];
+  const uint32_t np = p1 - p0;
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (uint32_t k = 0; k < np; ++k) {
+      const uint32_t id = order[p0 + k];
+      pid[k] = id;
+      cum[k] = acc;
+      acc += probs[id].geo.ncells;
+    }
+    cum[np] = acc;
+  }
+  __syncthreads();
+  const uint32_t total = cum[np];
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const bool odd = ((s + parity) & 1) != 0;
+    const S* src = odd ? bufB : bufA;
+    S* dst = odd ? bufA : bufB;
+    const C* wps = odd ? wpB : wpA;
+    C* wpd = odd ? wpA : wpB;
+    for (uint32_t t = threadIdx.x; t < total; t += blockDim.x) {
+      uint32_t k = 0, hi = np;   // cum[k] <= t < cum[k + 1]
+      while (hi - k > 1) {
+        const uint32_t mid = (k + hi) >> 1;
+        if (cum[mid] <= t) k = mid;
+        else hi = mid;
+      }
+      const uint32_t id = pid[k];
+      batch_cell<L, S, C>(probs[id], t - cum[k], src, dst, wps, wpd, lc, pps + id);
+    }
+    __syncthreads();
+  }
+}
+
+template <class L, typename S, typename C>
+static hipError_t batch_t(const BatchLaunch& a) {
+  constexpr int MAXT = batch_max_threads(sizeof(S));
+  if (a.threads > uint32_t(MAXT) || a.threads % 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_batch<L, S, C, MAXT>), dim3(a.nbins), dim3(a.threads), 0, a.stream, a.probs,
+                     static_cast<const ProbParams<C>*>(a.pps), a.bin_first, a.order, static_cast<S*>(a.bufA),
+                     static_cast<S*>(a.bufB), static_cast<C*>(a.wpA), static_cast<C*>(a.wpB),
+                     static_cast<const LatConsts<C>*>(a.lc), a.nsteps, a.parity);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(int velset, int storage, const BatchLaunch& a) {
+  if (velset == 1) {
+    if (storage == 0) return batch_t<D2Q37, double, double>(a);
+    if (storage == 1) return batch_t<D2Q37, float, float>(a);
+    if (storage == 2) return batch_t<D2Q37, _Float16, float>(a);
+  } else if (velset == 2) {
+    if (storage == 0) return batch_t<D3Q39, double, double>(a);
+    if (storage == 1) return batch_t<D3Q39, float, float>(a);
+    if (storage == 2) return batch_t<D3Q39, _Float16, float>(a);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace esbgk

@@ -1,0 +1,41 @@
+// Launchers of the HIP kernels (internal interface between the C ABI runtime
+// and kernels.hip / batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "params.h"
+
+namespace esbgk {
+
+// FP64 reduction slots: mass, energy, momentum x/y/z, sum |u - u_prev|^2,
+// sum |u|^2, number of invalid cells.
+constexpr int NRED = 8;
+
+struct StepArgs {
+  Geometry geo;
+  const void* src;      // populations read (storage type)
+  void* dst;            // populations written
+  const void* wp_src;   // wall partial sums read   [2 sides][3 layers][ncols]
+  void* wp_dst;         // wall partial sums written
+  const void* lc;       // LatConsts<C>*  of the step's compute type (device)
+  const void* pp;       // ProbParams<C>* of the step's compute type (device)
+  const void* lc64;     // LatConsts<double>*  (moments and explicit reductions)
+  const void* pp64;     // ProbParams<double>*
+  void* uprev;          // [D][ncells] velocity of the previous reduction (compute type)
+  int have_prev;
+  int reduce;           // step kernel: fuse the reductions
+  double* red_part;     // [workgroups][NRED]
+  hipStream_t stream;
+};
+
+hipError_t launch_step(int velset, int storage, const StepArgs& a);
+hipError_t launch_reduce(int velset, int storage, const StepArgs& a);
+hipError_t launch_reduce_finalize(const double* part, uint32_t nparts, double* out, hipStream_t stream);
+hipError_t launch_moments(int velset, int storage, const StepArgs& a, uint32_t c0, uint32_t count, double* out);
+hipError_t launch_init(int velset, int storage, const StepArgs& a, double r, const double* rho, const double* u,
+                       const double* T, const double* noise, double amp, uint32_t c0, uint32_t count);
+hipError_t launch_wall_partials(int velset, int storage, const StepArgs& a);
+
+}  // namespace esbgk

@@ -1,0 +1,385 @@
+// HIP kernels of the lattice ES-BGK step for gfx950, and their launchers.
+//
+// One thread updates one cell per step (pull scheme): it gathers the Q
+// populations that stream into the cell from buffer A, collides them
+// (cell.h) and writes the cell's Q post-collision populations to buffer B.
+// Populations are structure-of-arrays, [alpha][z][y][x], x fastest, so every
+// load and store of a wavefront covers 64 consecutive cells of one velocity.
+//
+// Streaming. For a wavefront whose cells are at least 3 cells away from every
+// edge, the source of velocity alpha is cell - shift_alpha with one shift per
+// velocity; the kernel folds that shift into the (uniform) base address of
+// the velocity plane, so all Q loads share one per-lane offset. Wavefronts
+// that touch an edge use per-lane wrapped coordinates and, across a wall, the
+// re-emitted populations of the diffuse wall (Sec. 3.2).
+//
+// Diffuse walls. rho_W of a wall-parallel column is the flux balance of
+// Sec. 3.2: the populations that cross the wall in one step (a population
+// with |e_n| = k crosses from the k layers next to the wall) over the matching
+// flux of S(T_w, u_w). Each step writes, for the cells of the three layers
+// next to a wall, the partial sums sum w h over the populations of that cell
+// that will cross the wall on the next step, computed from the values as
+// stored; the next step sums the three layers of a column. A population that
+// streams in from beyond the wall takes rho_W(source column) S(T_w, u_w).
+//
+// Reductions. The REDUCE variant also accumulates per cell, in FP64, the mass,
+// energy, momentum and the residual sums of the pre-collision state, reduces
+// them over the workgroup (wavefront shuffles, then LDS) and writes one
+// partial per workgroup; k_reduce_finalize sums the partials in a fixed order.
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "stream.h"
+
+namespace esbgk {
+
+constexpr int BLOCK = 256;
+
+// Compute type of the step for a storage type (FP32 for FP32/FP16 storage);
+// it is also the type of the wall partial sums and of the parameter blocks the
+// step reads.
+template <typename S> struct StepT { using type = float; };
+template <> struct StepT<double> { using type = double; };
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2). Give each XCD a contiguous range of tiles so that neighbouring tiles,
+// which share cache lines at their edges, are served by the same L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t per = nb >> 3;
+  if (b < (per << 3)) return (b & 7u) * per + (b >> 3);
+  return b;
+}
+
+// ---- FP64 reductions ---------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum NRED values over the workgroup (fixed order) and write them to out.
+__device__ __forceinline__ void block_reduce_write(double (&v)[NRED], double* __restrict__ out) {
+  __shared__ double lds[BLOCK / 64][NRED];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NRED; ++k) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) lds[wave][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NRED) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) s += lds[w][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+// Per-cell contributions: mass, energy, momentum (3), |u - u_prev|^2, |u|^2,
+// invalid-cell count. rho and T are formed in FP64 from their deviations.
+template <class L, typename C, typename U>
+__device__ __forceinline__ void cell_contrib(const CellState<L, C>& s, U* __restrict__ uprev, uint32_t cell,
+                                             uint32_t ncells, int have_prev, double (&v)[NRED]) {
+  constexpr int D = L::D;
+  const double rho = 1.0 + double(s.drho);
+  const double T = 1.0 + double(s.theta);
+  double uu = 0.0, du = 0.0;
+  v[0] = rho;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[2 + i] = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const double ui = double(s.u[i]);
+    v[2 + i] = rho * ui;
+    uu += ui * ui;
+    if (uprev) {
+      const double up = have_prev ? double(uprev[size_t(i) * ncells + cell]) : ui;
+      du += (ui - up) * (ui - up);
+      uprev[size_t(i) * ncells + cell] = U(ui);
+    }
+  }
+  v[1] = 0.5 * (rho * uu + rho * D * T);
+  v[5] = du;
+  v[6] = uu;
+  const bool bad = !(rho > 0.0) || !(T > 0.0) || !(uu < 1e300) || !(v[1] < 1e300);
+  v[7] = bad ? 1.0 : 0.0;
+}
+
+// ---- kernels ---------------------------------------------------------------
+
+// One time step: pull, collide, store, wall partial sums (and, when REDUCE,
+// the FP64 reductions of the pre-collision state).
+template <class L, typename S, bool REDUCE>
+__global__ void __launch_bounds__(BLOCK)
+k_step(Geometry geo, const S* __restrict__ src, S* __restrict__ dst, const typename StepT<S>::type* __restrict__ wp_src,
+       typename StepT<S>::type* __restrict__ wp_dst, const LatConsts<typename StepT<S>::type>* __restrict__ lc,
+       const ProbParams<typename StepT<S>::type>* __restrict__ pp, typename StepT<S>::type* __restrict__ uprev,
+       int have_prev, double* __restrict__ red_part) {
+  using C = typename StepT<S>::type;
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t cell = blk * BLOCK + threadIdx.x;
+  double v[NRED];
+  if (REDUCE) {
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) v[k] = 0.0;
+  }
+  if (cell < geo.ncells) {
+    const CellPos p = cell_pos(cell, geo);
+    const bool fast = __all(interior<L>(p, geo));
+    C h[L::Q];
+    gather<L, S, C, C>(h, src, geo, cell, p, wp_src, pp, fast);
+    CellState<L, C> st;
+    collide<L, C>(h, lc, pp, st);
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) dst[size_t(a) * geo.ncells + cell] = narrow<S, C>(h[a]);
+    if (geo.walls)
+      write_wall_partials<L, S, C>([&](int a) { return narrow<S, C>(h[a]); }, p, geo, lc, wp_dst);
+    if (REDUCE) cell_contrib<L, C, C>(st, uprev, cell, geo.ncells, have_prev, v);
+  }
+  if (REDUCE) block_reduce_write(v, red_part + size_t(blk) * NRED);
+}
+
+// Reductions of the current level without stepping (FP64 arithmetic).
+template <class L, typename S>
+__global__ void __launch_bounds__(BLOCK)
+k_reduce(Geometry geo, const S* __restrict__ src, const typename StepT<S>::type* __restrict__ wp,
+         const LatConsts<double>* __restrict__ lc, const ProbParams<double>* __restrict__ pp,
+         typename StepT<S>::type* __restrict__ uprev, int have_prev, double* __restrict__ red_part) {
+  using P = typename StepT<S>::type;
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t cell = blk * BLOCK + threadIdx.x;
+  double v[NRED];
+#pragma unroll
+  for (int k = 0; k < NRED; ++k) v[k] = 0.0;
+  if (cell < geo.ncells) {
+    const CellPos p = cell_pos(cell, geo);
+    const bool fast = __all(interior<L>(p, geo));
+    double h[L::Q];
+    gather<L, S, double, P>(h, src, geo, cell, p, wp, pp, fast);
+    RawMoments<L, double> m;
+    raw_moments<L, double>(h, lc, false, m);
+    CellState<L, double> st;
+    reconstruct<L, double>(m, lc, pp, st);
+    cell_contrib<L, double, P>(st, uprev, cell, geo.ncells, have_prev, v);
+  }
+  block_reduce_write(v, red_part + size_t(blk) * NRED);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_reduce_finalize(const double* __restrict__ part, uint32_t nparts,
+                                                           double* __restrict__ out) {
+  __shared__ double lds[BLOCK][NRED];
+  double v[NRED];
+#pragma unroll
+  for (int k = 0; k < NRED; ++k) v[k] = 0.0;
+  for (uint32_t b = threadIdx.x; b < nparts; b += BLOCK) {
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) v[k] += part[size_t(b) * NRED + k];
+  }
+#pragma unroll
+  for (int k = 0; k < NRED; ++k) lds[threadIdx.x][k] = v[k];
+  __syncthreads();
+  for (int stride = BLOCK / 2; stride > 0; stride >>= 1) {
+    if (int(threadIdx.x) < stride) {
+#pragma unroll
+      for (int k = 0; k < NRED; ++k) lds[threadIdx.x][k] += lds[threadIdx.x + stride][k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < NRED) out[threadIdx.x] = lds[0][threadIdx.x];
+}
+
+// Macroscopic fields of cells [c0, c0 + count), FP64 arithmetic from the
+// stored state, written as [F][count].
+template <class L, typename S>
+__global__ void __launch_bounds__(BLOCK)
+k_moments(Geometry geo, const S* __restrict__ src, const typename StepT<S>::type* __restrict__ wp,
+          const LatConsts<double>* __restrict__ lc, const ProbParams<double>* __restrict__ pp, uint32_t c0,
+          uint32_t count, double* __restrict__ out) {
+  using P = typename StepT<S>::type;
+  const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+  const bool act = i < count;
+  const uint32_t cell = c0 + (act ? i : 0u);
+  const CellPos p = cell_pos(cell, geo);
+  const bool fast = __all(act ? interior<L>(p, geo) : true);
+  if (!act) return;
+  double h[L::Q];
+  gather<L, S, double, P>(h, src, geo, cell, p, wp, pp, fast);
+  double f[nfields(L::D)];
+  cell_fields<L, double>(h, lc, pp, f);
+#pragma unroll
+  for (int k = 0; k < nfields(L::D); ++k) out[size_t(k) * count + i] = f[k];
+}
+
+// S(T, u)/w - 1 at velocity alpha (eq. feq0 at the order N of the lattice).
+template <class L>
+__device__ __forceinline__ double shat_m1(int a, double r, const double* u, double th) {
+  constexpr int D = L::D;
+  double cu = 0.0, uu = 0.0, cc = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const double ci = r * ecomp<L>(a, i);
+    cu += ci * u[i];
+    uu += u[i] * u[i];
+    cc += ci * ci;
+  }
+  double s = cu + 0.5 * (cu * cu - uu + th * (cc - D)) + cu / 6.0 * (cu * cu - 3.0 * uu + 3.0 * th * (cc - D - 2));
+  if (L::N >= 4) {
+    s += (cu * cu * cu * cu - 6.0 * cu * cu * uu + 3.0 * uu * uu) / 24.0 +
+         th / 4.0 * ((cc - D - 2) * (cu * cu - uu) - 2.0 * cu * cu) +
+         th * th / 8.0 * (cc * cc - 2.0 * (D + 2) * cc + D * (D + 2));
+  }
+  return s;
+}
+
+// Equilibrium initial state h = rho Shat (1 + amp xi) - 1 for cells
+// [c0, c0 + count); fields are [count] / [D][count] / [Q][count] or null.
+template <class L, typename S>
+__global__ void __launch_bounds__(BLOCK)
+k_init(Geometry geo, S* __restrict__ dst, double r, const double* __restrict__ rho, const double* __restrict__ u,
+       const double* __restrict__ T, const double* __restrict__ noise, double amp, uint32_t c0, uint32_t count) {
+  const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t cell = c0 + i;
+  const double drho = rho ? rho[i] - 1.0 : 0.0;
+  double uc[3] = {0.0, 0.0, 0.0};
+  if (u) {
+#pragma unroll
+    for (int d = 0; d < L::D; ++d) uc[d] = u[size_t(d) * count + i];
+  }
+  const double th = T ? T[i] - 1.0 : 0.0;
+#pragma unroll
+  for (int a = 0; a < L::Q; ++a) {
+    const double sm1 = shat_m1<L>(a, r, uc, th);
+    // rho Shat - 1 = drho Shat + (Shat - 1)
+    double hv = drho * (1.0 + sm1) + sm1;
+    if (noise) hv += (1.0 + hv) * amp * noise[size_t(a) * count + i];
+    dst[size_t(a) * geo.ncells + cell] = S(hv);
+  }
+}
+
+// Wall partial sums of the stored state (after the state was set); the same
+// arithmetic as the step kernel's, so a restart is bit-identical.
+template <class L, typename S>
+__global__ void __launch_bounds__(BLOCK)
+k_wall_partials(Geometry geo, const S* __restrict__ src, const LatConsts<typename StepT<S>::type>* __restrict__ lc,
+                typename StepT<S>::type* __restrict__ wp_dst) {
+  using P = typename StepT<S>::type;
+  constexpr int D = L::D;
+  const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= 6u * geo.ncols) return;
+  const uint32_t col = i % geo.ncols;
+  const uint32_t sk = i / geo.ncols;       // side * 3 + k
+  const int side = int(sk / 3), k = int(sk % 3);
+  const int nw = D == 2 ? int(geo.ny) : int(geo.nz);
+  const int cw = side == 0 ? k : nw - 1 - k;
+  const uint32_t cell = uint32_t(cw) * geo.ncols + col;   // the wall axis is the slowest
+  const CrossSums<L, S, P> cs =
+      cross_sums<L, S, P>([&](int a) { return src[size_t(a) * geo.ncells + cell]; }, lc);
+  wp_dst[sk * geo.ncols + col] = side == 0 ? layer_partial(cs.lo, k) : layer_partial(cs.hi, k);
+}
+
+// ---- launchers -----------------------------------------------------------------
+
+template <class L, typename S>
+static hipError_t step_t(const StepArgs& a) {
+  using C = typename StepT<S>::type;
+  const uint32_t nb = (a.geo.ncells + BLOCK - 1) / BLOCK;
+  if (a.reduce) {
+    hipLaunchKernelGGL((k_step<L, S, true>), dim3(nb), dim3(BLOCK), 0, a.stream, a.geo, static_cast<const S*>(a.src),
+                       static_cast<S*>(a.dst), static_cast<const C*>(a.wp_src), static_cast<C*>(a.wp_dst),
+                       static_cast<const LatConsts<C>*>(a.lc), static_cast<const ProbParams<C>*>(a.pp),
+                       static_cast<C*>(a.uprev), a.have_prev, a.red_part);
+  } else {
+    hipLaunchKernelGGL((k_step<L, S, false>), dim3(nb), dim3(BLOCK), 0, a.stream, a.geo,
+                       static_cast<const S*>(a.src), static_cast<S*>(a.dst), static_cast<const C*>(a.wp_src),
+                       static_cast<C*>(a.wp_dst), static_cast<const LatConsts<C>*>(a.lc),
+                       static_cast<const ProbParams<C>*>(a.pp), static_cast<C*>(a.uprev), a.have_prev, a.red_part);
+  }
+  return hipGetLastError();
+}
+
+template <class L, typename S>
+static hipError_t reduce_t(const StepArgs& a) {
+  using C = typename StepT<S>::type;
+  const uint32_t nb = (a.geo.ncells + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL((k_reduce<L, S>), dim3(nb), dim3(BLOCK), 0, a.stream, a.geo, static_cast<const S*>(a.src),
+                     static_cast<const C*>(a.wp_src), static_cast<const LatConsts<double>*>(a.lc64),
+                     static_cast<const ProbParams<double>*>(a.pp64), static_cast<C*>(a.uprev), a.have_prev,
+                     a.red_part);
+  return hipGetLastError();
+}
+
+template <class L, typename S>
+static hipError_t moments_t(const StepArgs& a, uint32_t c0, uint32_t count, double* out) {
+  using C = typename StepT<S>::type;
+  const uint32_t nb = (count + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL((k_moments<L, S>), dim3(nb), dim3(BLOCK), 0, a.stream, a.geo, static_cast<const S*>(a.src),
+                     static_cast<const C*>(a.wp_src), static_cast<const LatConsts<double>*>(a.lc64),
+                     static_cast<const ProbParams<double>*>(a.pp64), c0, count, out);
+  return hipGetLastError();
+}
+
+template <class L, typename S>
+static hipError_t init_t(const StepArgs& a, double r, const double* rho, const double* u, const double* T,
+                         const double* noise, double amp, uint32_t c0, uint32_t count) {
+  const uint32_t nb = (count + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL((k_init<L, S>), dim3(nb), dim3(BLOCK), 0, a.stream, a.geo, static_cast<S*>(a.dst), r, rho, u,
+                     T, noise, amp, c0, count);
+  return hipGetLastError();
+}
+
+template <class L, typename S>
+static hipError_t partials_t(const StepArgs& a) {
+  using C = typename StepT<S>::type;
+  const uint32_t n = 6u * a.geo.ncols;
+  const uint32_t nb = (n + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL((k_wall_partials<L, S>), dim3(nb), dim3(BLOCK), 0, a.stream, a.geo,
+                     static_cast<const S*>(a.src), static_cast<const LatConsts<C>*>(a.lc), static_cast<C*>(a.wp_dst));
+  return hipGetLastError();
+}
+
+#define ESBGK_DISPATCH(velset, storage, CALL)             \
+  do {                                                    \
+    if (velset == 1) {                                    \
+      using L = D2Q37;                                    \
+      if (storage == 0) { using S = double; return CALL; }   \
+      if (storage == 1) { using S = float; return CALL; }    \
+      if (storage == 2) { using S = _Float16; return CALL; } \
+    } else if (velset == 2) {                             \
+      using L = D3Q39;                                    \
+      if (storage == 0) { using S = double; return CALL; }   \
+      if (storage == 1) { using S = float; return CALL; }    \
+      if (storage == 2) { using S = _Float16; return CALL; } \
+    }                                                     \
+    return hipErrorInvalidValue;                          \
+  } while (0)
+
+hipError_t launch_step(int velset, int storage, const StepArgs& a) {
+  ESBGK_DISPATCH(velset, storage, (step_t<L, S>(a)));
+}
+
+hipError_t launch_reduce(int velset, int storage, const StepArgs& a) {
+  ESBGK_DISPATCH(velset, storage, (reduce_t<L, S>(a)));
+}
+
+hipError_t launch_reduce_finalize(const double* part, uint32_t nparts, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_reduce_finalize, dim3(1), dim3(BLOCK), 0, stream, part, nparts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(int velset, int storage, const StepArgs& a, uint32_t c0, uint32_t count, double* out) {
+  ESBGK_DISPATCH(velset, storage, (moments_t<L, S>(a, c0, count, out)));
+}
+
+hipError_t launch_init(int velset, int storage, const StepArgs& a, double r, const double* rho, const double* u,
+                       const double* T, const double* noise, double amp, uint32_t c0, uint32_t count) {
+  ESBGK_DISPATCH(velset, storage, (init_t<L, S>(a, r, rho, u, T, noise, amp, c0, count)));
+}
+
+hipError_t launch_wall_partials(int velset, int storage, const StepArgs& a) {
+  ESBGK_DISPATCH(velset, storage, (partials_t<L, S>(a)));
+}
+
+}  // namespace esbgk

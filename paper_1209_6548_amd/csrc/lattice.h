@@ -1,0 +1,57 @@
+// Integer velocity sets of the on-lattice quadratures, as compile-time tables.
+//
+// The lattice ES-BGK model (Sec. 2.2) evaluates the distribution at the
+// abscissae c_alpha = r e_alpha of a Gauss-Hermite quadrature. On-lattice
+// streaming needs integer e_alpha; the two sets used here are D2Q37 (exact to
+// degree 9, carries the N = 4 expansion the paper uses) and D3Q39 (exact to
+// degree 7, carries N = 3). Only the integer vectors are compile-time; the
+// scale r and the weights are derived on the host at start-up (tables.cpp)
+// and read by the kernels from device memory.
+//
+// Velocity order (shared with the population I/O of the C ABI): index 0 is
+// the rest velocity, indices 1..P the vectors whose first non-zero component
+// is positive, sorted by |e|^2 and then by descending tuple order, and index
+// alpha + P holds -e_alpha. The kernels exploit the (alpha, alpha + P) pairing
+// to split every polynomial in e into its even and odd parts.
+#pragma once
+
+namespace esbgk {
+
+struct D2Q37 {
+  static constexpr int D = 2;
+  static constexpr int Q = 37;
+  static constexpr int P = 18;   // number of (e, -e) pairs
+  static constexpr int N = 4;    // Hermite order carried
+  // representatives e_1..e_P (the opposites follow at +P)
+  static constexpr int E[P][3] = {
+      {1, 0, 0},  {0, 1, 0},                          // |e|^2 = 1
+      {1, 1, 0},  {1, -1, 0},                         // 2
+      {2, 0, 0},  {0, 2, 0},                          // 4
+      {2, 1, 0},  {2, -1, 0}, {1, 2, 0}, {1, -2, 0},  // 5
+      {2, 2, 0},  {2, -2, 0},                         // 8
+      {3, 0, 0},  {0, 3, 0},                          // 9
+      {3, 1, 0},  {3, -1, 0}, {1, 3, 0}, {1, -3, 0},  // 10
+  };
+};
+
+struct D3Q39 {
+  static constexpr int D = 3;
+  static constexpr int Q = 39;
+  static constexpr int P = 19;
+  static constexpr int N = 3;
+  static constexpr int E[P][3] = {
+      {1, 0, 0},  {0, 1, 0},  {0, 0, 1},                                  // 1
+      {1, 1, 1},  {1, 1, -1}, {1, -1, 1}, {1, -1, -1},                    // 3
+      {2, 0, 0},  {0, 2, 0},  {0, 0, 2},                                  // 4
+      {2, 2, 0},  {2, 0, 2},  {2, 0, -2}, {2, -2, 0}, {0, 2, 2}, {0, 2, -2},  // 8
+      {3, 0, 0},  {0, 3, 0},  {0, 0, 3},                                  // 9
+  };
+};
+
+// Component a of velocity alpha (0 <= alpha < Q), including the opposites.
+template <class L>
+__host__ __device__ constexpr int ecomp(int alpha, int a) {
+  return alpha == 0 ? 0 : (alpha <= L::P ? L::E[alpha - 1][a] : -L::E[alpha - 1 - L::P][a]);
+}
+
+}  // namespace esbgk

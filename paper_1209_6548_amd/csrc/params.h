@@ -1,0 +1,68 @@
+// Parameter blocks shared by the host runtime and the kernels.
+//
+// LatConsts and ProbParams live in device memory (inside the caller's
+// workspace) and are read by the kernels through uniform pointers, so they
+// arrive in scalar registers and a captured HIP graph stays valid when the
+// gas, wall or force parameters change.
+#pragma once
+
+#include <stdint.h>
+
+namespace esbgk {
+
+constexpr int QMAX = 39;
+
+// Lattice constants: quadrature weights and the velocity scale c = r e.
+template <typename C>
+struct LatConsts {
+  C w[QMAX];
+  C r;
+};
+
+// Per-problem constants of one step (derived on the host in FP64).
+//   dt      time step dx/r
+//   hs      half shift: dt/2 (trapezoid) or 0 (Euler)
+//   hsdt    hs/dt
+//   xcoef   dt Pr / Kn, so that dt/tau = xcoef rho T^(1-varpi)
+//   omv     1 - varpi
+//   invPr   1/Pr
+//   b       1 - 1/Pr
+//   g       body force
+//   force   g != 0
+// Walls (side 0 low, 1 high), Ehat = S(T_w, u_w)/w at every velocity:
+//   Em1     Ehat - 1
+//   Ehat    Ehat
+//   K0      (sum_{alpha leaving} |e_n| w_alpha)/den - 1
+//   invden  1/den, den = sum_{alpha entering} |e_n| w_alpha Ehat_alpha
+// so that rho_W - 1 = K0 + invden * (sum of the partial sums of w h over the
+// populations that leave through the wall).
+template <typename C>
+struct ProbParams {
+  C dt, hs, hsdt, xcoef, omv, invPr, b;
+  C g[3];
+  int force;
+  C Em1[2][QMAX];
+  C Ehat[2][QMAX];
+  C K0[2], invden[2];
+};
+
+// Division by a run-time constant d for n < 2^31: q = (umulhi(n, m) + n) >> l
+// with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1.
+struct FastDiv {
+  uint32_t m, l;
+};
+
+// Geometry of one lattice (kernel argument, fixed for a handle's life).
+struct Geometry {
+  uint32_t nx, ny, nz;       // extents
+  uint32_t ncells;           // nx*ny*nz
+  uint32_t ncols;            // cells of one layer across the wall axis
+  uint32_t walls;            // 1: diffuse walls across the last axis
+  uint32_t nxy;              // nx*ny
+  FastDiv div_nx, div_ny;    // division by nx and by ny
+};
+
+// Fields per cell returned by the moments kernel: rho, u[D], T, sigma, q[D].
+constexpr int nfields(int D) { return D == 2 ? 9 : 14; }
+
+}  // namespace esbgk

@@ -1,0 +1,45 @@
+// Host-side constants: velocity sets, per-problem parameters, fast division.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "params.h"
+
+namespace esbgk {
+
+struct HostLattice {
+  int velset = 0, D = 0, Q = 0, N = 0, P = 0;
+  double r = 0;
+  std::vector<int> e;     // Q x 3
+  std::vector<double> w;  // Q
+};
+
+// Derived once per process; null if the derivation failed.
+const HostLattice* host_lattice(int velset);
+
+// S(T, u)/w - 1 at velocity a (eq. feq0, rho = 1, order N of the lattice).
+double shat_minus_one(const HostLattice& lat, int a, double T, const double u[3]);
+
+// FP64 version of ProbParams.
+struct HostProblem {
+  double dt, hs, hsdt, xcoef, omv, invPr, b;
+  double g[3];
+  int force;
+  double Em1[2][QMAX];
+  double Ehat[2][QMAX];
+  double K0[2], invden[2];
+};
+
+HostProblem make_problem(const HostLattice& lat, int n_ref, int scheme, double Kn, double Pr, double varpi,
+                         const double g[3], const double Tw[2], const double uw[2][3]);
+
+template <typename C>
+void pack_params(const HostProblem& h, int Q, ProbParams<C>& d);
+template <typename C>
+void pack_lattice(const HostLattice& lat, LatConsts<C>& d);
+
+FastDiv make_fastdiv(uint32_t d);
+
+}  // namespace esbgk

@@ -1,0 +1,90 @@
+"""CPU checks of the C ABI library: it loads, exports every function that
+include/esbgk.h declares, derives the same velocity sets as the oracle and
+validates shapes on the host (no GPU work)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "esbgk.h")
+LIB = os.path.join(ROOT, "paper_1209_6548_amd", "libesbgk.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libesbgk.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(esbgk_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for n in ("esbgk_create", "esbgk_step", "esbgk_read_moments", "esbgk_set_gas", "esbgk_set_wall",
+              "esbgk_set_body_force", "esbgk_batch_step", "esbgk_reduce"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("name", ["D2Q37", "D3Q39"])
+def test_library_tables_equal_the_oracle(name):
+    from oracle import quadrature
+    from paper_1209_6548_amd import lattice_info
+    info = lattice_info(name)
+    vs = quadrature.velocity_set(name)
+    assert info["Q"] == vs.Q and info["D"] == vs.D and info["N"] == vs.N
+    np.testing.assert_array_equal(info["e"], vs.e)
+    assert info["r"] == pytest.approx(vs.r, rel=1e-15)
+    np.testing.assert_allclose(info["w"], vs.w, rtol=1e-14)
+
+
+def test_workspace_bytes_validates_shapes():
+    from paper_1209_6548_amd import binding as B
+    lib = B.lib()
+    ok = B.Shape(B.D2Q37, 64, 32, 1, 1, B.F32, B.TRAPEZOID, 0)
+    n = lib.esbgk_workspace_bytes(ctypes.byref(ok))
+    # two population buffers of 37 x 2048 floats at least
+    assert n >= 2 * 37 * 64 * 32 * 4
+    bad = [B.Shape(3, 8, 8, 1, 0, 0, 0, 0),            # unknown set
+           B.Shape(B.D2Q37, 8, 8, 2, 0, 0, 0, 0),      # nz != 1 in 2-D
+           B.Shape(B.D2Q37, 8, 5, 1, 1, 0, 0, 0),      # wall axis < 6
+           B.Shape(B.D3Q39, 8, 8, 0, 0, 0, 0, 0),      # empty
+           B.Shape(B.D2Q37, 8, 8, 1, 0, 3, 0, 0),      # storage
+           B.Shape(B.D2Q37, 8, 8, 1, 0, 0, 2, 0),      # scheme
+           B.Shape(B.D3Q39, 2048, 2048, 1024, 0, 0, 0, 0)]  # >= 2^31 cells
+    for s in bad:
+        assert lib.esbgk_workspace_bytes(ctypes.byref(s)) == 0
+
+
+def test_create_rejects_missing_workspace():
+    from paper_1209_6548_amd import binding as B
+    lib = B.lib()
+    s = B.Shape(B.D2Q37, 8, 8, 1, 0, B.F64, 0, 0)
+    ctx = ctypes.c_void_p()
+    assert lib.esbgk_create(ctypes.byref(s), None, 0, None, ctypes.byref(ctx)) == B.E_NOMEM
+    assert not ctx.value
+
+
+def test_fast_division_constants():
+    # the kernels divide cell indices by nx and ny with (umulhi(n, m) + n) >> l
+    from paper_1209_6548_amd import binding  # noqa: F401  (library loads)
+    for d in [1, 2, 3, 4, 5, 7, 16, 32, 100, 255, 256, 257, 1000, 1024, 4097, 65537, 1 << 20, (1 << 31) - 1]:
+        l = 0
+        while (1 << l) < d:
+            l += 1
+        m = ((1 << 32) * ((1 << l) - d)) // d + 1
+        rng = np.random.default_rng(d)
+        ns = np.concatenate([rng.integers(0, 1 << 31, 2000), [0, d - 1, d, d + 1, (1 << 31) - 1]])
+        for n in ns:
+            n = int(n)
+            q = (((n * m) >> 32) + n) >> l
+            assert q == n // d, (d, n)
