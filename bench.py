@@ -165,7 +165,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-main", action="store_true", help="time only the headline FP32 run")
+    ap.add_argument("--profile", action="store_true",
+                    help="headline kernel only, preceded by a 1 GiB device copy whose known size calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--storage", default="f32", choices=("f32", "f64", "f16"),
+                    help="storage of the headline run (default f32)")
     args = ap.parse_args()
+    if args.profile:
+        args.only_main, args.no_cpu = True, True
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -177,9 +184,17 @@ def main():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
     r = lattice_info("D2Q37")["r"]
-    cfg = workloads.poiseuille_thermal_1024(r, storage="f32")
-    log(f"headline: {cfg['name']} f32, {args.steps} steps after {args.warmup} warmup")
-    main_run = bench_single(cfg, "f32", args.steps, args.warmup)
+    cfg = workloads.poiseuille_thermal_1024(r, storage=args.storage)
+    if args.profile:
+        n = 1 << 28                                   # 2^28 floats = 1 GiB each way
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 1073741824 bytes read, 1073741824 bytes written")
+        del a, b
+    log(f"headline: {cfg['name']} {args.storage}, {args.steps} steps after {args.warmup} warmup")
+    main_run = bench_single(cfg, args.storage, args.steps, args.warmup)
     log(f"f32: {main_run['mlups']:.0f} MLUPS, {main_run['algorithmic_GBs']:.0f} GB/s")
     variants = {}
     if not args.only_main:
@@ -198,14 +213,14 @@ def main():
     line = {
         "metric": "MLUPS", "value": round(main_run["mlups"], 1), "unit": "MLUPS",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.storage,
         "data": "synthetic",
         "config": {"workload": cfg["name"], "velset": "D2Q37", "order_N": 4, "cells": 1024 * 1024,
-                   "storage": "f32 deviational", "Kn": cfg["Kn"], "Pr": cfg["Pr"], "walls_T": list(cfg["T_w"]),
+                   "storage": f"{args.storage} deviational", "Kn": cfg["Kn"], "Pr": cfg["Pr"], "walls_T": list(cfg["T_w"]),
                    "g_x_nondim": cfg["g"][0], "scheme": "trapezoid"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_step<D2Q37, float>", "bytes_per_cell": main_run["bytes_per_cell"]},
+                     "kernel": f"k_step<D2Q37, {args.storage}>", "bytes_per_cell": main_run["bytes_per_cell"]},
         "cpu_baseline": cpu,
         "variants": variants,
     }

@@ -45,6 +45,7 @@ bool valid_shape(const esbgk_shape* s, std::string* why) {
     if (nw < 6) return fail("the wall axis needs at least 6 cells");
   }
   if (s->storage < ESBGK_F64 || s->storage > ESBGK_F16) return fail("storage must be F64, F32 or F16");
+  if (n * storage_size(s->storage) >= (uint64_t(1) << 32)) return fail("one velocity plane must be < 4 GiB");
   if (s->scheme != ESBGK_TRAPEZOID && s->scheme != ESBGK_EULER) return fail("scheme must be TRAPEZOID or EULER");
   if (s->n_ref < 0) return fail("n_ref must be >= 0");
   return true;

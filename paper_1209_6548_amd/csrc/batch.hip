@@ -33,7 +33,7 @@ __device__ __forceinline__ void batch_cell(const BatchProblem& bp, uint32_t cell
   CellState<L, C> st;
   collide<L, C>(h, lc, pp, st);
 #pragma unroll
-  for (int a = 0; a < L::Q; ++a) dst[size_t(a) * geo.ncells + cell] = narrow<S, C>(h[a]);
+  for (int a = 0; a < L::Q; ++a) st_plane(dst + size_t(a) * geo.ncells, cell * uint32_t(sizeof(S)), narrow<S, C>(h[a]));
   write_wall_partials<L, S, C>([&](int a) { return narrow<S, C>(h[a]); }, p, geo, lc, wpd);
 }
 

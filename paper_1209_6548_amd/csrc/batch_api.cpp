@@ -45,6 +45,8 @@ bool valid_problem(const esbgk_problem& p, const esbgk_problem& first, std::stri
   const int nw = s.velset == ESBGK_D2Q37 ? s.ny : s.nz;
   if (nw < 6) return fail("the wall axis needs at least 6 cells");
   if (uint64_t(s.nx) * s.ny * s.nz >= (uint64_t(1) << 31)) return fail("problem too large");
+  if (s.storage >= 0 && s.storage <= 2 && uint64_t(s.nx) * s.ny * s.nz * ssize(s.storage) >= (uint64_t(1) << 32))
+    return fail("one velocity plane must be < 4 GiB");
   if (s.storage < 0 || s.storage > 2 || (s.scheme != 0 && s.scheme != 1) || s.n_ref < 0) return fail("bad shape");
   if (!(p.Kn > 0.0) || !(p.Pr >= 2.0 / 3.0 - 1e-12) || !(p.varpi >= 0.5 && p.varpi <= 1.0))
     return fail("bad gas parameters");

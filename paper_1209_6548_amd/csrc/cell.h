@@ -35,6 +35,10 @@ namespace esbgk {
 
 // ---- small helpers ---------------------------------------------------------
 
+// Fused multiply-add in the compute type (no promotion of float to double).
+__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // acc + k x for an integer k known at compile time after unrolling; zero terms
 // vanish without relying on fast-math.
 template <typename C>
@@ -42,7 +46,7 @@ __device__ __forceinline__ C addk(C acc, C x, int k) {
   if (k == 0) return acc;
   if (k == 1) return acc + x;
   if (k == -1) return acc - x;
-  return __builtin_fma(x, C(k), acc);
+  return fmac(x, C(k), acc);
 }
 
 __device__ __forceinline__ constexpr int fact(int n) { return n <= 1 ? 1 : n * fact(n - 1); }
@@ -383,7 +387,7 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const LatConsts<C>* __rest
   }
 
   const C omw = C(1) - om;
-  h[0] = __builtin_fma(omw, h[0], K0);
+  h[0] = fmac(omw, h[0], K0);
 #pragma unroll
   for (int p = 1; p <= P; ++p) {
     const int e[3] = {L::E[p - 1][0], L::E[p - 1][1], L::E[p - 1][2]};
@@ -411,8 +415,8 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const LatConsts<C>* __rest
             for (int l = k; l < D; ++l)
               E = addk(E, K4[i][j][k][l], mult4(i, j, k, l) * e[i] * e[j] * e[k] * e[l]);
     }
-    const C hp = __builtin_fma(omw, h[p], E + O);
-    const C hm = __builtin_fma(omw, h[p + P], E - O);
+    const C hp = fmac(omw, h[p], E + O);
+    const C hm = fmac(omw, h[p + P], E - O);
     h[p] = hp;
     h[p + P] = hm;
   }

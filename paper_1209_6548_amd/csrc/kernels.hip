@@ -133,7 +133,7 @@ k_step(Geometry geo, const S* __restrict__ src, S* __restrict__ dst, const typen
     CellState<L, C> st;
     collide<L, C>(h, lc, pp, st);
 #pragma unroll
-    for (int a = 0; a < L::Q; ++a) dst[size_t(a) * geo.ncells + cell] = narrow<S, C>(h[a]);
+    for (int a = 0; a < L::Q; ++a) st_plane(dst + size_t(a) * geo.ncells, cell * uint32_t(sizeof(S)), narrow<S, C>(h[a]));
     if (geo.walls)
       write_wall_partials<L, S, C>([&](int a) { return narrow<S, C>(h[a]); }, p, geo, lc, wp_dst);
     if (REDUCE) cell_contrib<L, C, C>(st, uprev, cell, geo.ncells, have_prev, v);

@@ -19,6 +19,19 @@ namespace esbgk {
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv d) { return (__umulhi(n, d.m) + n) >> d.l; }
 
+// Load / store element boff / sizeof(S) of a velocity plane. The plane base is
+// uniform across the wavefront and boff is a 32-bit byte offset (planes are
+// smaller than 4 GiB), so the access is a scalar-base + vector-offset
+// instruction with no per-lane 64-bit address arithmetic.
+template <typename S>
+__device__ __forceinline__ S ld_plane(const S* __restrict__ plane, uint32_t boff) {
+  return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(plane) + boff);
+}
+template <typename S>
+__device__ __forceinline__ void st_plane(S* __restrict__ plane, uint32_t boff, S v) {
+  *reinterpret_cast<S*>(reinterpret_cast<char*>(plane) + boff) = v;
+}
+
 __device__ __forceinline__ int wrapc(int v, int n) {
   // v in [-3, n + 2], n >= 1
   if (v < 0) v += n;
@@ -65,7 +78,7 @@ __device__ __forceinline__ void gather(C (&h)[L::Q], const S* __restrict__ src, 
       const long shift = long(ecomp<L>(a, 2)) * long(geo.nxy) + long(ecomp<L>(a, 1)) * long(geo.nx) +
                          long(ecomp<L>(a, 0));
       const S* plane = src + size_t(a) * geo.ncells - shift;
-      h[a] = widen<C, S>(plane[cell]);
+      h[a] = widen<C, S>(ld_plane(plane, cell * uint32_t(sizeof(S))));
     }
     return;
   }
@@ -96,7 +109,7 @@ __device__ __forceinline__ void gather(C (&h)[L::Q], const S* __restrict__ src, 
       h[a] = em1 + eh * drw;
     } else {
       const uint32_t off = (uint32_t(sz) * geo.ny + uint32_t(sy)) * geo.nx + uint32_t(sx);
-      h[a] = widen<C, S>(src[size_t(a) * geo.ncells + off]);
+      h[a] = widen<C, S>(ld_plane(src + size_t(a) * geo.ncells, off * uint32_t(sizeof(S))));
     }
   }
 }
