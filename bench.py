@@ -195,7 +195,7 @@ def main():
         del a, b
     log(f"headline: {cfg['name']} {args.storage}, {args.steps} steps after {args.warmup} warmup")
     main_run = bench_single(cfg, args.storage, args.steps, args.warmup)
-    log(f"f32: {main_run['mlups']:.0f} MLUPS, {main_run['algorithmic_GBs']:.0f} GB/s")
+    log(f"{args.storage}: {main_run['mlups']:.0f} MLUPS, {main_run['algorithmic_GBs']:.0f} GB/s")
     variants = {}
     if not args.only_main:
         for st in ("f64", "f16"):
@@ -203,6 +203,18 @@ def main():
             log(f"{st}: {variants[st]['mlups']:.0f} MLUPS, {variants[st]['algorithmic_GBs']:.0f} GB/s")
         variants["batched_channels"] = bench_batch(r, max(50, args.steps), args.warmup)
         log(f"batch: {variants['batched_channels']['mlups']:.0f} MLUPS")
+        r3 = lattice_info("D3Q39")["r"]
+        # 3-D workloads (timed from the rest state: the step's work does not depend on it)
+        box = dict(name="shear_wave_256^3", velset="D3Q39", dims=(256, 256, 256), walls=False, Kn=0.02,
+                   Pr=2 / 3, varpi=0.5, g=(0.0, 0.0, 0.0))
+        for st in ("f32", "f16"):
+            key = f"shear_wave_256^3_{st}"
+            variants[key] = bench_single(box, st, max(20, args.steps // 4), 5)
+            log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
+        ch = workloads.channel_3d(r3)
+        key = f"{ch['name']}_f16"
+        variants[key] = bench_single(ch, "f16", max(10, args.steps // 10), 3)
+        log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")

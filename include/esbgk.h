@@ -146,6 +146,12 @@ int esbgk_set_state(esbgk_ctx* ctx, const void* h_raw, size_t nbytes);
  * (esbgk_set_reduce_interval) the step also forms the FP64 reductions. */
 int esbgk_step(esbgk_ctx* ctx, int64_t n);
 
+/* Runs of `steps` consecutive step launches (even, default 32) are captured
+ * once per starting buffer in a HIP graph and replayed on the handle's
+ * stream; 0 disables graphs (one launch per step). Steps that carry a fused
+ * reduction are always launched directly. Results are identical either way. */
+int esbgk_set_graph_steps(esbgk_ctx* ctx, int steps);
+
 /* Macroscopic fields of eq. mac at the current level, FP64 [F][cells] host:
  * rho, u[D], T, sigma (trace-free, components xx,xy,yy or
  * xx,xy,xz,yy,yz,zz), q[D]. F = 9 (2-D) or 14 (3-D); *F receives it. */

@@ -69,6 +69,7 @@ def lib():
             "esbgk_get_state": (I, [P, P, SZ]),
             "esbgk_set_state": (I, [P, P, SZ]),
             "esbgk_step": (I, [P, I64]),
+            "esbgk_set_graph_steps": (I, [P, I]),
             "esbgk_read_moments": (I, [P, DP, P]),
             "esbgk_reduce": (I, [P, DP]),
             "esbgk_set_reduce_interval": (I, [P, I64]),
@@ -231,6 +232,9 @@ class Lattice:
 
     def step(self, n=1):
         self._check(lib().esbgk_step(self._ctx, int(n)), "step")
+
+    def set_graph_steps(self, steps):
+        self._check(lib().esbgk_set_graph_steps(self._ctx, int(steps)), "set_graph_steps")
 
     @property
     def steps_done(self):

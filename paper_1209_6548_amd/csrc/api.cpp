@@ -114,6 +114,12 @@ struct esbgk_ctx {
   LatConsts<double> lc64{};
   LatConsts<float> lc32{};
 
+  // HIP graphs of graph_steps consecutive step launches, one per starting
+  // buffer, captured on a private stream and replayed on the caller's stream
+  int graph_steps = 32;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+
   char* at(size_t off) const { return ws + off; }
   bool f64() const { return shape.storage == ESBGK_F64; }
 };
@@ -137,13 +143,13 @@ int hip_fail(esbgk_ctx* c, hipError_t e, const char* where) {
     if (_e != hipSuccess) return hip_fail(ctx, _e, where); \
   } while (0)
 
-StepArgs base_args(const esbgk_ctx* c) {
+StepArgs args_at(const esbgk_ctx* c, int cur) {
   StepArgs a{};
   a.geo = c->geo;
-  a.src = c->at(c->lay.pop[c->cur]);
-  a.dst = c->at(c->lay.pop[1 - c->cur]);
-  a.wp_src = c->at(c->lay.wp[c->cur]);
-  a.wp_dst = c->at(c->lay.wp[1 - c->cur]);
+  a.src = c->at(c->lay.pop[cur]);
+  a.dst = c->at(c->lay.pop[1 - cur]);
+  a.wp_src = c->at(c->lay.wp[cur]);
+  a.wp_dst = c->at(c->lay.wp[1 - cur]);
   a.lc = c->at(c->lay.lc);
   a.pp = c->at(c->lay.pp);
   a.lc64 = c->at(c->lay.lc64);
@@ -154,6 +160,49 @@ StepArgs base_args(const esbgk_ctx* c) {
   a.red_part = reinterpret_cast<double*>(c->at(c->lay.red_part));
   a.stream = c->stream;
   return a;
+}
+
+StepArgs base_args(const esbgk_ctx* c) { return args_at(c, c->cur); }
+
+void drop_graphs(esbgk_ctx* c) {
+  for (int p = 0; p < 2; ++p) {
+    if (c->graph[p]) (void)hipGraphExecDestroy(c->graph[p]);
+    c->graph[p] = nullptr;
+  }
+}
+
+// Capture graph_steps plain step launches starting from buffer `parity`.
+int build_graph(esbgk_ctx* c, int parity) {
+  if (!c->cap) {
+    hipError_t e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      c->cap = nullptr;
+      return hip_fail(c, e, "create capture stream");
+    }
+  }
+  HIP_OR_FAIL(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed), "begin capture");
+  int cur = parity;
+  hipError_t le = hipSuccess;
+  for (int i = 0; i < c->graph_steps && le == hipSuccess; ++i) {
+    StepArgs a = args_at(c, cur);
+    a.stream = c->cap;
+    le = launch_step(c->shape.velset, c->shape.storage, a);
+    cur ^= 1;
+  }
+  hipGraph_t g = nullptr;
+  hipError_t ee = hipStreamEndCapture(c->cap, &g);
+  if (le != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(c, le, "capture step");
+  }
+  if (ee != hipSuccess) return hip_fail(c, ee, "end capture");
+  hipError_t ie = hipGraphInstantiate(&c->graph[parity], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    c->graph[parity] = nullptr;
+    return hip_fail(c, ie, "instantiate graph");
+  }
+  return ESBGK_OK;
 }
 
 int upload_params(esbgk_ctx* c) {
@@ -291,7 +340,17 @@ int esbgk_create(const esbgk_shape* shape, void* d_workspace, size_t ws_bytes, v
 
 int esbgk_destroy(esbgk_ctx* ctx) {
   if (!ctx) return ESBGK_E_INVALID;
+  drop_graphs(ctx);
+  if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   delete ctx;
+  return ESBGK_OK;
+}
+
+int esbgk_set_graph_steps(esbgk_ctx* c, int steps) {
+  CHECK_CTX(c);
+  if (steps < 0 || steps % 2) return set_err(c, ESBGK_E_INVALID, "graph steps must be even and >= 0");
+  if (steps != c->graph_steps) drop_graphs(c);
+  c->graph_steps = steps;
   return ESBGK_OK;
 }
 
@@ -489,7 +548,29 @@ int esbgk_step(esbgk_ctx* c, int64_t n) {
   if (n < 0) return set_err(c, ESBGK_E_INVALID, "n must be >= 0");
   if (!c->state_set) return set_err(c, ESBGK_E_STATE, "no state set");
   const uint32_t nblocks = (c->geo.ncells + BLOCK - 1) / BLOCK;
-  for (int64_t i = 0; i < n; ++i) {
+  const int64_t G = c->graph_steps;
+  if (G > 0 && n > 0) {
+    // capture both graphs up front so that the first replay does not wait
+    // for the host
+    for (int p = 0; p < 2; ++p)
+      if (!c->graph[p]) {
+        const int rc = build_graph(c, p);
+        if (rc) return rc;
+      }
+  }
+  while (n > 0) {
+    // a whole graph when no fused reduction falls inside its G steps
+    const bool red_inside = c->R > 0 && ((c->steps / c->R) + 1) * c->R <= c->steps + G;
+    if (G > 0 && n >= G && !red_inside) {
+      if (!c->graph[c->cur]) {
+        const int rc = build_graph(c, c->cur);
+        if (rc) return rc;
+      }
+      HIP_OR_FAIL(c, hipGraphLaunch(c->graph[c->cur], c->stream), "graph launch");
+      c->steps += G;   // G is even: the state ends in the same buffer
+      n -= G;
+      continue;
+    }
     StepArgs a = base_args(c);
     const bool red = c->R > 0 && ((c->steps + 1) % c->R == 0);
     a.reduce = red ? 1 : 0;
@@ -502,6 +583,7 @@ int esbgk_step(esbgk_ctx* c, int64_t n) {
     }
     c->cur ^= 1;
     c->steps += 1;
+    n -= 1;
   }
   return ESBGK_OK;
 }

@@ -29,7 +29,7 @@ __device__ __forceinline__ void batch_cell(const BatchProblem& bp, uint32_t cell
   C* wpd = wpdb + bp.wp_off;
   const CellPos p = cell_pos(cell, geo);
   C h[L::Q];
-  gather<L, S, C, C>(h, src, geo, cell, p, wps, pp, false);
+  gather<L, S, C, C>(h, src, geo, cell, p, wps, pp, PULL_WALL);
   CellState<L, C> st;
   collide<L, C>(h, lc, pp, st);
 #pragma unroll

@@ -39,6 +39,11 @@ namespace esbgk {
 __device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// 1/x: the hardware reciprocal (1 ulp) in FP32, a correctly rounded division
+// in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // acc + k x for an integer k known at compile time after unrolling; zero terms
 // vanish without relying on fast-math.
 template <typename C>
@@ -164,7 +169,7 @@ __device__ __forceinline__ void reconstruct(const RawMoments<L, C>& m, const Lat
   const C hs = pp->hs;
   s.drho = m.drho;
   s.rho = C(1) + m.drho;
-  s.irho = C(1) / s.rho;
+  s.irho = recip(s.rho);
   C uu = C(0), gu = C(0);
 #pragma unroll
   for (int i = 0; i < D; ++i) {
@@ -186,9 +191,9 @@ __device__ __forceinline__ void reconstruct(const RawMoments<L, C>& m, const Lat
   const C T = C(1) + s.theta;
   const C x = pp->xcoef * s.rho * pow_pos<C>(T, pp->omv);
   s.xh = x * pp->hsdt;
-  s.omega = x / (C(1) + s.xh);
+  s.omega = x * recip(C(1) + s.xh);
   s.phi = C(1) - s.omega * pp->hsdt;
-  const C kap = C(1) / (C(1) + s.xh * pp->invPr);
+  const C kap = recip(C(1) + s.xh * pp->invPr);
   C Sg[3][3];
   C trS = C(0);
 #pragma unroll
@@ -239,7 +244,7 @@ __device__ __forceinline__ void physical_a3(const RawMoments<L, C>& m, const Cel
                                             const C* g, bool force, C (&a3)[3][3][3]) {
   constexpr int D = L::D;
   const C r3 = r * r * r;
-  const C inv = C(1) / (C(1) + s.xh);
+  const C inv = recip(C(1) + s.xh);
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll

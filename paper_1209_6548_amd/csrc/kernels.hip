@@ -127,9 +127,9 @@ k_step(Geometry geo, const S* __restrict__ src, S* __restrict__ dst, const typen
   }
   if (cell < geo.ncells) {
     const CellPos p = cell_pos(cell, geo);
-    const bool fast = __all(interior<L>(p, geo));
+    const PullMode mode = pull_mode<L>(p, geo);
     C h[L::Q];
-    gather<L, S, C, C>(h, src, geo, cell, p, wp_src, pp, fast);
+    gather<L, S, C, C>(h, src, geo, cell, p, wp_src, pp, mode);
     CellState<L, C> st;
     collide<L, C>(h, lc, pp, st);
 #pragma unroll
@@ -155,9 +155,9 @@ k_reduce(Geometry geo, const S* __restrict__ src, const typename StepT<S>::type*
   for (int k = 0; k < NRED; ++k) v[k] = 0.0;
   if (cell < geo.ncells) {
     const CellPos p = cell_pos(cell, geo);
-    const bool fast = __all(interior<L>(p, geo));
+    const PullMode mode = pull_mode<L>(p, geo);
     double h[L::Q];
-    gather<L, S, double, P>(h, src, geo, cell, p, wp, pp, fast);
+    gather<L, S, double, P>(h, src, geo, cell, p, wp, pp, mode);
     RawMoments<L, double> m;
     raw_moments<L, double>(h, lc, false, m);
     CellState<L, double> st;
@@ -202,10 +202,10 @@ k_moments(Geometry geo, const S* __restrict__ src, const typename StepT<S>::type
   const bool act = i < count;
   const uint32_t cell = c0 + (act ? i : 0u);
   const CellPos p = cell_pos(cell, geo);
-  const bool fast = __all(act ? interior<L>(p, geo) : true);
+  const PullMode mode = pull_mode<L>(p, geo);   // inactive lanes repeat cell c0
   if (!act) return;
   double h[L::Q];
-  gather<L, S, double, P>(h, src, geo, cell, p, wp, pp, fast);
+  gather<L, S, double, P>(h, src, geo, cell, p, wp, pp, mode);
   double f[nfields(L::D)];
   cell_fields<L, double>(h, lc, pp, f);
 #pragma unroll

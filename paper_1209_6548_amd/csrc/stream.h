@@ -22,14 +22,18 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv d) { return (__umul
 // Load / store element boff / sizeof(S) of a velocity plane. The plane base is
 // uniform across the wavefront and boff is a 32-bit byte offset (planes are
 // smaller than 4 GiB), so the access is a scalar-base + vector-offset
-// instruction with no per-lane 64-bit address arithmetic.
+// instruction with no per-lane 64-bit address arithmetic. FP64 populations
+// are stored non-temporally (measured 6% faster for FP64 on MI355X; slower
+// for the narrower types, which keep the default policy).
 template <typename S>
 __device__ __forceinline__ S ld_plane(const S* __restrict__ plane, uint32_t boff) {
   return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(plane) + boff);
 }
 template <typename S>
 __device__ __forceinline__ void st_plane(S* __restrict__ plane, uint32_t boff, S v) {
-  *reinterpret_cast<S*>(reinterpret_cast<char*>(plane) + boff) = v;
+  S* p = reinterpret_cast<S*>(reinterpret_cast<char*>(plane) + boff);
+  if constexpr (sizeof(S) == 8) __builtin_nontemporal_store(v, p);
+  else *p = v;
 }
 
 __device__ __forceinline__ int wrapc(int v, int n) {
@@ -63,16 +67,35 @@ __device__ __forceinline__ bool interior(const CellPos& p, const Geometry& geo) 
   return ok;
 }
 
-// Pull the Q populations that stream into cell p. fast: every lane of the
-// wavefront is interior, so velocity alpha comes from cell - shift_alpha and
-// the shift folds into the (uniform) plane base address. P is the type of the
-// wall partial sums, C the compute type.
+// At least 3 layers from both walls (always true without walls).
+template <class L>
+__device__ __forceinline__ bool off_walls(const CellPos& p, const Geometry& geo) {
+  if (!geo.walls) return true;
+  const int cw = L::D == 2 ? p.y : p.z;
+  const int nw = L::D == 2 ? int(geo.ny) : int(geo.nz);
+  return cw >= 3 && cw < nw - 3;
+}
+
+// How a wavefront pulls: every lane interior (shifted plane bases, no
+// per-velocity arithmetic); some lane at a periodic edge but none near a wall
+// (per-lane wrapped offsets); some lane near a wall (wrapped offsets plus wall
+// ghosts).
+enum PullMode { PULL_FAST = 0, PULL_WRAP = 1, PULL_WALL = 2 };
+
+template <class L>
+__device__ __forceinline__ PullMode pull_mode(const CellPos& p, const Geometry& geo) {
+  if (__all(interior<L>(p, geo))) return PULL_FAST;
+  return __all(off_walls<L>(p, geo)) ? PULL_WRAP : PULL_WALL;
+}
+
+// Pull the Q populations that stream into cell p. P is the type of the wall
+// partial sums, C the compute type.
 template <class L, typename S, typename C, typename P>
 __device__ __forceinline__ void gather(C (&h)[L::Q], const S* __restrict__ src, const Geometry& geo,
                                        uint32_t cell, const CellPos& p, const P* __restrict__ wp,
-                                       const ProbParams<C>* __restrict__ pp, bool fast) {
+                                       const ProbParams<C>* __restrict__ pp, PullMode mode) {
   constexpr int D = L::D, Q = L::Q;
-  if (fast) {
+  if (mode == PULL_FAST) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       const long shift = long(ecomp<L>(a, 2)) * long(geo.nxy) + long(ecomp<L>(a, 1)) * long(geo.nx) +
@@ -82,25 +105,35 @@ __device__ __forceinline__ void gather(C (&h)[L::Q], const S* __restrict__ src, 
     }
     return;
   }
+  // wrapped coordinates of the source for shifts -3..3, pre-scaled to element
+  // offsets; along the wall axis they are left unwrapped (out of range = beyond
+  // a wall)
   const int nx = int(geo.nx), ny = int(geo.ny), nz = int(geo.nz);
   const bool walls = geo.walls != 0;
-  int xs[7], ys[7], zs[7];
+  int xo[7], yo[7], zo[7];
 #pragma unroll
   for (int s = -3; s <= 3; ++s) {
-    xs[s + 3] = wrapc(p.x - s, nx);
-    ys[s + 3] = (D == 2 && walls) ? p.y - s : wrapc(p.y - s, ny);
-    zs[s + 3] = (D == 3) ? (walls ? p.z - s : wrapc(p.z - s, nz)) : 0;
+    xo[s + 3] = wrapc(p.x - s, nx);
+    yo[s + 3] = ((D == 2 && walls) ? p.y - s : wrapc(p.y - s, ny)) * nx;
+    zo[s + 3] = (D == 3) ? ((walls ? p.z - s : wrapc(p.z - s, nz)) * int(geo.nxy)) : 0;
   }
+  if (mode == PULL_WRAP) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const uint32_t off = uint32_t(xo[ecomp<L>(a, 0) + 3] + yo[ecomp<L>(a, 1) + 3] + zo[ecomp<L>(a, 2) + 3]);
+      h[a] = widen<C, S>(ld_plane(src + size_t(a) * geo.ncells, off * uint32_t(sizeof(S))));
+    }
+    return;
+  }
+  const int cw = D == 2 ? p.y : p.z;
+  const int nw = D == 2 ? ny : nz;
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
-    const int sx = xs[ecomp<L>(a, 0) + 3];
-    const int sy = ys[ecomp<L>(a, 1) + 3];
-    const int sz = zs[ecomp<L>(a, 2) + 3];
-    const int sw = D == 2 ? sy : sz;
-    const int nw = D == 2 ? ny : nz;
+    const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), ez = ecomp<L>(a, 2);
+    const int sw = cw - (D == 2 ? ey : ez);
     if (walls && (sw < 0 || sw >= nw)) {
       const int side = sw < 0 ? 0 : 1;
-      const uint32_t col = D == 2 ? uint32_t(sx) : uint32_t(sy) * geo.nx + uint32_t(sx);
+      const uint32_t col = uint32_t(xo[ex + 3] + (D == 2 ? 0 : yo[ey + 3]));
       const P* q = wp + uint32_t(side) * 3u * geo.ncols + col;
       const C part = C(q[0]) + C(q[geo.ncols]) + C(q[2u * geo.ncols]);
       const C drw = (side ? pp->K0[1] : pp->K0[0]) + (side ? pp->invden[1] : pp->invden[0]) * part;
@@ -108,7 +141,7 @@ __device__ __forceinline__ void gather(C (&h)[L::Q], const S* __restrict__ src, 
       const C eh = side ? pp->Ehat[1][a] : pp->Ehat[0][a];
       h[a] = em1 + eh * drw;
     } else {
-      const uint32_t off = (uint32_t(sz) * geo.ny + uint32_t(sy)) * geo.nx + uint32_t(sx);
+      const uint32_t off = uint32_t(xo[ex + 3] + yo[ey + 3] + zo[ez + 3]);
       h[a] = widen<C, S>(ld_plane(src + size_t(a) * geo.ncells, off * uint32_t(sizeof(S))));
     }
   }

@@ -121,6 +121,26 @@ def test_fused_reduction_equals_explicit():
     assert rb0["step"] == 3
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_graph_replay_equals_direct_launches(storage):
+    cfg = H.small_cfg("D2Q37", (40, 24), True)
+    prob = H.oracle_problem(cfg)
+    a = H.gpu_lattice(cfg, storage)
+    b = H.gpu_lattice(cfg, storage)
+    _start(cfg, a, prob)
+    _start(cfg, b, prob)
+    b.set_graph_steps(0)                   # one launch per step
+    a.set_graph_steps(8)
+    for lat in (a, b):
+        lat.set_reduce_interval(13)        # fused reductions inside and between graphs
+        lat.step(3)                        # odd: graphs start from the other buffer too
+        lat.step(57)
+    np.testing.assert_array_equal(a.get_populations(), b.get_populations())
+    ra, rb = a.last_reduction(), b.last_reduction()
+    assert ra["step"] == rb["step"] == 51
+    assert ra["energy"] == rb["energy"] and ra["residual"] == rb["residual"]
+
+
 @pytest.mark.parametrize("storage", ["f64", "f16"])
 def test_checkpoint_restart_is_bit_identical(storage):
     cfg = H.small_cfg("D3Q39", (6, 5, 9), True)
