@@ -174,7 +174,8 @@ int esbgk_last_reduction(esbgk_ctx* ctx, double out[8]);
 /* Steps taken since the state was last set. */
 int64_t esbgk_steps_done(const esbgk_ctx* ctx);
 
-/* Text of the last error on this handle ("" if none). */
+/* Text of the last error on this handle ("" if none); with NULL, the reason
+ * the last esbgk_create on this thread failed. */
 const char* esbgk_last_error(const esbgk_ctx* ctx);
 
 /* ---- Batches of independent channels -----------------------------------

@@ -46,9 +46,15 @@ _lib = None
 
 
 def lib():
-    """The loaded library; raises if it has not been built."""
+    """The loaded library; raises if it has not been built.
+
+    PyTorch is imported first: it carries its own HIP runtime with the same
+    soname as the system one, so loading torch first makes libesbgk.so bind
+    to that runtime instead of starting a second one in the process (two
+    runtimes cannot share the device, the streams or the memory)."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1209_6548_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
@@ -169,7 +175,8 @@ class Lattice:
         rc = L.esbgk_create(ctypes.byref(self.shape), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
                             _stream_ptr(self.device), ctypes.byref(self._ctx))
         if rc:
-            raise EsbgkError(rc, "create")
+            msg = L.esbgk_last_error(None)
+            raise EsbgkError(rc, f"create: {msg.decode() if msg else ''}")
 
     # -- plumbing --
     def _check(self, rc, what):

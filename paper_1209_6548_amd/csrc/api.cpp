@@ -126,6 +126,10 @@ struct esbgk_ctx {
 
 namespace {
 
+// Message of the last failed esbgk_create on this thread (no handle exists to
+// hold it); returned by esbgk_last_error(NULL).
+thread_local std::string g_create_error;
+
 int set_err(esbgk_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
   return code;
@@ -316,20 +320,26 @@ int esbgk_create(const esbgk_shape* shape, void* d_workspace, size_t ws_bytes, v
   g.div_nx = make_fastdiv(g.nx);
   g.div_ny = make_fastdiv(g.ny);
   pack_lattice<double>(*lat, c->lc64);
-  int rc = hipMemcpyAsync(c->at(lay.lc64), &c->lc64, sizeof(c->lc64), hipMemcpyHostToDevice, c->stream) == hipSuccess
-               ? ESBGK_OK : ESBGK_E_HIP;
-  if (rc == ESBGK_OK && !c->f64()) {
+  int rc = ESBGK_OK;
+  auto hip = [&](hipError_t e, const char* where) {
+    if (rc == ESBGK_OK && e != hipSuccess) {
+      rc = ESBGK_E_HIP;
+      g_create_error = std::string("create: ") + where + ": " + hipGetErrorString(e);
+    }
+  };
+  hip(hipMemcpyAsync(c->at(lay.lc64), &c->lc64, sizeof(c->lc64), hipMemcpyHostToDevice, c->stream), "upload lattice");
+  if (!c->f64()) {
     pack_lattice<float>(*lat, c->lc32);
-    rc = hipMemcpyAsync(c->at(lay.lc), &c->lc32, sizeof(c->lc32), hipMemcpyHostToDevice, c->stream) == hipSuccess
-             ? ESBGK_OK : ESBGK_E_HIP;
+    hip(hipMemcpyAsync(c->at(lay.lc), &c->lc32, sizeof(c->lc32), hipMemcpyHostToDevice, c->stream), "upload lattice");
   }
-  if (rc == ESBGK_OK) rc = upload_params(c);
+  if (rc == ESBGK_OK) {
+    rc = upload_params(c);
+    if (rc) g_create_error = c->err;
+  }
   // wall partial sums start at zero (a state must be set before stepping)
-  if (rc == ESBGK_OK &&
-      hipMemsetAsync(c->at(lay.wp[0]), 0, lay.wp[1] - lay.wp[0], c->stream) != hipSuccess) rc = ESBGK_E_HIP;
-  if (rc == ESBGK_OK &&
-      hipMemsetAsync(c->at(lay.wp[1]), 0, lay.wp[1] - lay.wp[0], c->stream) != hipSuccess) rc = ESBGK_E_HIP;
-  if (rc == ESBGK_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = ESBGK_E_HIP;
+  hip(hipMemsetAsync(c->at(lay.wp[0]), 0, lay.wp[1] - lay.wp[0], c->stream), "clear wall sums");
+  hip(hipMemsetAsync(c->at(lay.wp[1]), 0, lay.wp[1] - lay.wp[0], c->stream), "clear wall sums");
+  hip(hipStreamSynchronize(c->stream), "synchronize");
   if (rc != ESBGK_OK) {
     delete c;
     return rc;
@@ -639,6 +649,6 @@ int esbgk_last_reduction(esbgk_ctx* c, double out[8]) {
 
 int64_t esbgk_steps_done(const esbgk_ctx* c) { return c ? c->steps : -1; }
 
-const char* esbgk_last_error(const esbgk_ctx* c) { return c ? c->err.c_str() : "null handle"; }
+const char* esbgk_last_error(const esbgk_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
 }  // extern "C"

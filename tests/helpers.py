@@ -12,7 +12,11 @@ Two metrics per moment field X (rho, u, T, sigma, q):
   X_rest = 1 for rho and T and 0 otherwise: the error relative to the size of
   the signal the field carries. Its floor is the storage rounding of the
   populations (ulp of |h| ~ 0.1-0.3 per step) over the signal, so its gates
-  are looser: 1e-10, 1e-4, 3e-2.
+  are looser: 1e-10, 1e-4, 3e-2. A field whose signal is below ten times the
+  scale-relative gate (a density change of 1e-8 in a weakly forced FP32
+  channel, say) sits at the rounding floor that the other fields' larger
+  deviations leave in it; its error is divided by that ten-fold gate
+  instead, so it must still be a thousand times below the scale gate.
 """
 
 import numpy as np
@@ -60,6 +64,7 @@ def oracle_fields(f, prob, cells=None):
 
 TOL_SCALE = {"f64": 1e-12, "f32": 1e-6, "f16": 1e-3}
 TOL_SIGNAL = {"f64": 1e-10, "f32": 1e-4, "f16": 3e-2}
+SIGNAL_FLOOR = {k: 10.0 * v for k, v in TOL_SCALE.items()}
 
 
 def field_abs_errors(gpu, orc):
@@ -69,7 +74,7 @@ def field_abs_errors(gpu, orc):
 def assert_parity(gpu, orc, storage, scale_tol=None, signal_tol=None):
     """Both metrics within their gates; returns them for reporting."""
     ea = field_abs_errors(gpu, orc)
-    er = field_errors(gpu, orc)
+    er = field_errors(gpu, orc, SIGNAL_FLOOR[storage])
     st = TOL_SCALE[storage] if scale_tol is None else scale_tol
     sg = TOL_SIGNAL[storage] if signal_tol is None else signal_tol
     assert max(ea.values()) < st, ("scale-relative", ea)
@@ -77,10 +82,10 @@ def assert_parity(gpu, orc, storage, scale_tol=None, signal_tol=None):
     return ea, er
 
 
-def field_errors(gpu, orc):
+def field_errors(gpu, orc, floor=0.0):
     out = {}
     for k, rest in REST.items():
-        den = np.max(np.abs(np.asarray(orc[k]) - rest))
+        den = max(float(np.max(np.abs(np.asarray(orc[k]) - rest))), floor)
         num = np.max(np.abs(np.asarray(gpu[k]) - np.asarray(orc[k])))
         out[k] = num / den if den > 0 else num
     return out
@@ -107,3 +112,25 @@ def small_cfg(velset, dims, walls, force=True, Kn=0.05, Pr=2 / 3, varpi=0.5):
             cfg["u_w"] = ((-0.04, 0.02, 0.0), (0.05, -0.01, 0.0))
         cfg["T_w"] = (0.98, 1.04)
     return cfg
+
+
+class StoredPopulations:
+    """Read-only (Q, M) view of the physical populations f = w (1 + h) over a
+    raw stored state (h in its storage dtype), converting only the entries an
+    index asks for. Lets the oracle step sampled cells of grids whose FP64
+    populations would not fit in host memory."""
+
+    def __init__(self, raw, Q, M, dtype, w):
+        self.h = np.frombuffer(raw, dtype=dtype, count=Q * M).reshape(Q, M)
+        self.w = np.asarray(w, dtype=np.float64)
+        self.shape = (Q, M)
+
+    def __getitem__(self, key):
+        a, b = key
+        vals = np.asarray(self.h[a, b], dtype=np.float64)
+        return self.w[a] * (1.0 + vals)
+
+
+def ulp(x, dtype):
+    """Spacing of dtype at |x| (elementwise), as float64."""
+    return np.spacing(np.abs(np.asarray(x, dtype=np.float64)).astype(dtype)).astype(np.float64)
