@@ -29,6 +29,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_traffic_poiseuille1024.json")
 
 
 def log(msg):
@@ -127,6 +128,25 @@ def bench_batch(r, steps, warmup, fp64_sample=16):
     return out
 
 
+def measured_traffic(storage):
+    """HBM bytes per step launch on the headline workload from the FETCH_SIZE /
+    WRITE_SIZE counters (calibrated against a copy of known size), or None if
+    the step kernel's sources changed since they were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+        return int(rec["per_launch_bytes"][storage]["hbm_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(r, budget_s=20.0):
     """The FP64 oracle on a bounded sample of the same workload: the 1024 x
     1024 channel's per-cell work (D2Q37, walls, force, N = 4) on a 256 x 256
@@ -222,6 +242,7 @@ def main():
         log(f"cpu: {cpu['value']:.3f} MLUPS")
     ms = main_run["ms_per_step"]
     achieved = main_run["algorithmic_GBs"]
+    traffic = measured_traffic(args.storage)
     line = {
         "metric": "MLUPS", "value": round(main_run["mlups"], 1), "unit": "MLUPS",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
@@ -231,7 +252,9 @@ def main():
                    "storage": f"{args.storage} deviational", "Kn": cfg["Kn"], "Pr": cfg["Pr"], "walls_T": list(cfg["T_w"]),
                    "g_x_nondim": cfg["g"][0], "scheme": "trapezoid"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_over_algorithmic": (round(traffic / (main_run["bytes_per_cell"] * 1024 * 1024), 4)
+                                                  if traffic else None),
                      "kernel": f"k_step<D2Q37, {args.storage}>", "bytes_per_cell": main_run["bytes_per_cell"]},
         "cpu_baseline": cpu,
         "variants": variants,

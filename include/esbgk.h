@@ -90,7 +90,9 @@ int esbgk_lattice_info(int velset, int* Q, int* D, int* N, double* r, int* e, do
 
 /* Bytes of device workspace a lattice of this shape needs (0 if the shape is
  * invalid). The caller allocates it (e.g. torch.empty(n, dtype=uint8)),
- * 256-byte aligned. */
+ * 256-byte aligned. The populations live in it slice-blocked: for every
+ * layer of the last axis, the Q velocity planes of that layer side by side;
+ * a shape whose one layer of populations reaches 4 GiB is invalid. */
 size_t esbgk_workspace_bytes(const esbgk_shape* shape);
 
 /* Bind a workspace and a HIP stream (hipStream_t, NULL = default stream) to a
@@ -131,9 +133,10 @@ int esbgk_init_equilibrium(esbgk_ctx* ctx, const double* rho, const double* u,
 int esbgk_set_populations(esbgk_ctx* ctx, const double* h);
 int esbgk_get_populations(esbgk_ctx* ctx, double* h);
 
-/* Raw state (storage bytes of the populations + the step counter) for
- * checkpoint / restart; esbgk_state_bytes gives the size. Restoring and
- * stepping is bit-identical to never having saved. */
+/* Raw state for checkpoint / restart: the stored populations h in the
+ * storage type as [Q][cells] (cells numbered x fastest, independent of the
+ * device layout), then the step counter (int64); esbgk_state_bytes gives the
+ * size. Restoring and stepping is bit-identical to never having saved. */
 size_t esbgk_state_bytes(const esbgk_ctx* ctx);
 int esbgk_get_state(esbgk_ctx* ctx, void* h_raw, size_t nbytes);
 int esbgk_set_state(esbgk_ctx* ctx, const void* h_raw, size_t nbytes);

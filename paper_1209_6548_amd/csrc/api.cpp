@@ -45,7 +45,11 @@ bool valid_shape(const esbgk_shape* s, std::string* why) {
     if (nw < 6) return fail("the wall axis needs at least 6 cells");
   }
   if (s->storage < ESBGK_F64 || s->storage > ESBGK_F16) return fail("storage must be F64, F32 or F16");
-  if (n * storage_size(s->storage) >= (uint64_t(1) << 32)) return fail("one velocity plane must be < 4 GiB");
+  if (!host_lattice(s->velset)) return fail("velocity set tables unavailable");
+  Geometry g;
+  if (!make_geometry(s->velset == ESBGK_D2Q37 ? 2 : 3, s->velset == ESBGK_D2Q37 ? 37 : 39, uint32_t(s->nx),
+                     uint32_t(s->ny), uint32_t(s->nz), s->walls != 0, true, storage_size(s->storage), g))
+    return fail("lattice too large for the slice layout (one slice of the populations must be < 4 GiB)");
   if (s->scheme != ESBGK_TRAPEZOID && s->scheme != ESBGK_EULER) return fail("scheme must be TRAPEZOID or EULER");
   if (s->n_ref < 0) return fail("n_ref must be >= 0");
   return true;
@@ -55,6 +59,17 @@ int ncols_of(const esbgk_shape* s) {
   return s->velset == ESBGK_D2Q37 ? s->nx : s->nx * s->ny;
 }
 
+// The single-lattice geometry (slice-blocked layout); the shape is valid.
+Geometry geometry_of(const esbgk_shape* s) {
+  const HostLattice* lat = host_lattice(s->velset);
+  Geometry g;
+  make_geometry(lat->D, lat->Q, uint32_t(s->nx), uint32_t(s->ny), uint32_t(s->nz), s->walls != 0, true,
+                storage_size(s->storage), g);
+  return g;
+}
+
+uint32_t slot_blocks(const Geometry& g) { return uint32_t((uint64_t(g.nslices) * g.ipad + BLOCK - 1) / BLOCK); }
+
 Layout layout_of(const esbgk_shape* s) {
   const HostLattice* lat = host_lattice(s->velset);
   Layout L{};
@@ -62,11 +77,13 @@ Layout layout_of(const esbgk_shape* s) {
   const size_t ss = storage_size(s->storage), cs = compute_size(s->storage);
   const size_t Q = size_t(lat->Q), D = size_t(lat->D);
   const size_t ncols = size_t(ncols_of(s));
-  const size_t nblocks = (cells + BLOCK - 1) / BLOCK;
+  const Geometry g = geometry_of(s);
+  const size_t nblocks = slot_blocks(g);
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
-  L.pop[0] = take(Q * cells * ss);
-  L.pop[1] = take(Q * cells * ss);
+  const size_t pop_bytes = size_t(g.nslices) * g.sstride * ss;
+  L.pop[0] = take(pop_bytes);
+  L.pop[1] = take(pop_bytes);
   L.wp[0] = take(6 * ncols * cs);
   L.wp[1] = take(6 * ncols * cs);
   L.lc = take(cs == 8 ? sizeof(LatConsts<double>) : sizeof(LatConsts<float>));
@@ -309,16 +326,7 @@ int esbgk_create(const esbgk_shape* shape, void* d_workspace, size_t ws_bytes, v
   c->ws = static_cast<char*>(d_workspace);
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->n_ref = shape->n_ref > 0 ? shape->n_ref : (shape->walls ? (lat->D == 2 ? shape->ny : shape->nz) : shape->nx);
-  Geometry& g = c->geo;
-  g.nx = uint32_t(shape->nx);
-  g.ny = uint32_t(shape->ny);
-  g.nz = uint32_t(shape->nz);
-  g.ncells = g.nx * g.ny * g.nz;
-  g.ncols = uint32_t(ncols_of(shape));
-  g.walls = uint32_t(shape->walls);
-  g.nxy = g.nx * g.ny;
-  g.div_nx = make_fastdiv(g.nx);
-  g.div_ny = make_fastdiv(g.ny);
+  c->geo = geometry_of(shape);
   pack_lattice<double>(*lat, c->lc64);
   int rc = ESBGK_OK;
   auto hip = [&](hipError_t e, const char* where) {
@@ -467,6 +475,22 @@ void widen_plane(const unsigned char* in, size_t n, double* out) {
   for (size_t i = 0; i < n; ++i) out[i] = double(s[i]);
 }
 
+// Copy velocity plane q of the current state between a dense host array
+// [cells] of the storage type and the slice-blocked device layout.
+hipError_t plane_to_device(esbgk_ctx* c, int q, const void* host) {
+  const Geometry& g = c->geo;
+  const size_t ss = storage_size(c->shape.storage);
+  return hipMemcpy2DAsync(c->at(c->lay.pop[c->cur]) + size_t(q) * g.pstride * ss, size_t(g.sstride) * ss, host,
+                          size_t(g.inner) * ss, size_t(g.inner) * ss, g.nslices, hipMemcpyHostToDevice, c->stream);
+}
+
+hipError_t plane_to_host(esbgk_ctx* c, int q, void* host) {
+  const Geometry& g = c->geo;
+  const size_t ss = storage_size(c->shape.storage);
+  return hipMemcpy2DAsync(host, size_t(g.inner) * ss, c->at(c->lay.pop[c->cur]) + size_t(q) * g.pstride * ss,
+                          size_t(g.sstride) * ss, size_t(g.inner) * ss, g.nslices, hipMemcpyDeviceToHost, c->stream);
+}
+
 }  // namespace
 
 extern "C" {
@@ -474,21 +498,18 @@ extern "C" {
 int esbgk_set_populations(esbgk_ctx* c, const double* h) {
   CHECK_CTX(c);
   if (!h) return set_err(c, ESBGK_E_INVALID, "h is null");
-  const size_t cells = c->geo.ncells, ss = storage_size(c->shape.storage);
-  char* dst = c->at(c->lay.pop[c->cur]);
+  const size_t cells = c->geo.ncells;
   std::vector<unsigned char> buf;
   for (int q = 0; q < c->lat->Q; ++q) {
     const double* src = h + size_t(q) * cells;
     if (c->shape.storage == ESBGK_F64) {
-      HIP_OR_FAIL(c, hipMemcpyAsync(dst + size_t(q) * cells * ss, src, cells * ss, hipMemcpyHostToDevice, c->stream),
-                  "set populations");
+      HIP_OR_FAIL(c, plane_to_device(c, q, src), "set populations");
       HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "set populations");
       continue;
     }
     if (c->shape.storage == ESBGK_F32) narrow_plane<float>(src, cells, buf);
     else narrow_plane<_Float16>(src, cells, buf);
-    HIP_OR_FAIL(c, hipMemcpyAsync(dst + size_t(q) * cells * ss, buf.data(), cells * ss, hipMemcpyHostToDevice,
-                                  c->stream), "set populations");
+    HIP_OR_FAIL(c, plane_to_device(c, q, buf.data()), "set populations");
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "set populations");
   }
   int rc = refresh_partials(c);
@@ -507,11 +528,9 @@ int esbgk_get_populations(esbgk_ctx* c, double* h) {
   if (!c->state_set) return set_err(c, ESBGK_E_STATE, "no state set");
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "get populations");
   const size_t cells = c->geo.ncells, ss = storage_size(c->shape.storage);
-  const char* src = c->at(c->lay.pop[c->cur]);
   std::vector<unsigned char> buf(cells * ss);
   for (int q = 0; q < c->lat->Q; ++q) {
-    HIP_OR_FAIL(c, hipMemcpyAsync(buf.data(), src + size_t(q) * cells * ss, cells * ss, hipMemcpyDeviceToHost,
-                                  c->stream), "get populations");
+    HIP_OR_FAIL(c, plane_to_host(c, q, buf.data()), "get populations");
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "get populations");
     double* o = h + size_t(q) * cells;
     if (c->shape.storage == ESBGK_F64) widen_plane<double>(buf.data(), cells, o);
@@ -531,8 +550,10 @@ int esbgk_get_state(esbgk_ctx* c, void* h_raw, size_t nbytes) {
   if (!h_raw || nbytes != esbgk_state_bytes(c)) return set_err(c, ESBGK_E_INVALID, "state buffer size mismatch");
   if (!c->state_set) return set_err(c, ESBGK_E_STATE, "no state set");
   const size_t pop = nbytes - sizeof(int64_t);
+  const size_t plane = pop / size_t(c->lat->Q);
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "get state");
-  HIP_OR_FAIL(c, hipMemcpyAsync(h_raw, c->at(c->lay.pop[c->cur]), pop, hipMemcpyDeviceToHost, c->stream), "get state");
+  for (int q = 0; q < c->lat->Q; ++q)
+    HIP_OR_FAIL(c, plane_to_host(c, q, static_cast<char*>(h_raw) + size_t(q) * plane), "get state");
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "get state");
   std::memcpy(static_cast<char*>(h_raw) + pop, &c->steps, sizeof(int64_t));
   return ESBGK_OK;
@@ -542,8 +563,10 @@ int esbgk_set_state(esbgk_ctx* c, const void* h_raw, size_t nbytes) {
   CHECK_CTX(c);
   if (!h_raw || nbytes != esbgk_state_bytes(c)) return set_err(c, ESBGK_E_INVALID, "state buffer size mismatch");
   const size_t pop = nbytes - sizeof(int64_t);
+  const size_t plane = pop / size_t(c->lat->Q);
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "set state");
-  HIP_OR_FAIL(c, hipMemcpyAsync(c->at(c->lay.pop[c->cur]), h_raw, pop, hipMemcpyHostToDevice, c->stream), "set state");
+  for (int q = 0; q < c->lat->Q; ++q)
+    HIP_OR_FAIL(c, plane_to_device(c, q, static_cast<const char*>(h_raw) + size_t(q) * plane), "set state");
   int rc = refresh_partials(c);
   if (rc) return rc;
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "set state");
@@ -557,7 +580,7 @@ int esbgk_step(esbgk_ctx* c, int64_t n) {
   CHECK_CTX(c);
   if (n < 0) return set_err(c, ESBGK_E_INVALID, "n must be >= 0");
   if (!c->state_set) return set_err(c, ESBGK_E_STATE, "no state set");
-  const uint32_t nblocks = (c->geo.ncells + BLOCK - 1) / BLOCK;
+  const uint32_t nblocks = slot_blocks(c->geo);
   const int64_t G = c->graph_steps;
   if (G > 0 && n > 0) {
     // capture both graphs up front so that the first replay does not wait
@@ -623,7 +646,7 @@ int esbgk_reduce(esbgk_ctx* c, double out[8]) {
   CHECK_CTX(c);
   if (!out) return set_err(c, ESBGK_E_INVALID, "out is null");
   if (!c->state_set) return set_err(c, ESBGK_E_STATE, "no state set");
-  const uint32_t nblocks = (c->geo.ncells + BLOCK - 1) / BLOCK;
+  const uint32_t nblocks = slot_blocks(c->geo);
   StepArgs a = base_args(c);
   HIP_OR_FAIL(c, launch_reduce(c->shape.velset, c->shape.storage, a), "reduce");
   HIP_OR_FAIL(c, launch_reduce_finalize(a.red_part, nblocks, reinterpret_cast<double*>(c->at(c->lay.red_out)),

@@ -29,11 +29,12 @@ __device__ __forceinline__ void batch_cell(const BatchProblem& bp, uint32_t cell
   C* wpd = wpdb + bp.wp_off;
   const CellPos p = cell_pos(cell, geo);
   C h[L::Q];
-  gather<L, S, C, C>(h, src, geo, cell, p, wps, pp, PULL_WALL);
+  gather_lane<L, S, C, C, uint32_t>(h, src, geo, p, wps, pp);
   CellState<L, C> st;
   collide<L, C>(h, lc, pp, st);
+  const uint32_t elem = uint32_t(cell_elem<L>(p, geo));
 #pragma unroll
-  for (int a = 0; a < L::Q; ++a) st_plane(dst + size_t(a) * geo.ncells, cell * uint32_t(sizeof(S)), narrow<S, C>(h[a]));
+  for (int a = 0; a < L::Q; ++a) dst[a * geo.pstride + elem] = narrow<S, C>(h[a]);
   write_wall_partials<L, S, C>([&](int a) { return narrow<S, C>(h[a]); }, p, geo, lc, wpd);
 }
 

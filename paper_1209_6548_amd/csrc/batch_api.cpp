@@ -45,8 +45,8 @@ bool valid_problem(const esbgk_problem& p, const esbgk_problem& first, std::stri
   const int nw = s.velset == ESBGK_D2Q37 ? s.ny : s.nz;
   if (nw < 6) return fail("the wall axis needs at least 6 cells");
   if (uint64_t(s.nx) * s.ny * s.nz >= (uint64_t(1) << 31)) return fail("problem too large");
-  if (s.storage >= 0 && s.storage <= 2 && uint64_t(s.nx) * s.ny * s.nz * ssize(s.storage) >= (uint64_t(1) << 32))
-    return fail("one velocity plane must be < 4 GiB");
+  if (uint64_t(s.nx) * s.ny * s.nz * 39u >= (uint64_t(1) << 32))
+    return fail("a problem's populations must number < 2^32 (32-bit offsets)");
   if (s.storage < 0 || s.storage > 2 || (s.scheme != 0 && s.scheme != 1) || s.n_ref < 0) return fail("bad shape");
   if (!(p.Kn > 0.0) || !(p.Pr >= 2.0 / 3.0 - 1e-12) || !(p.varpi >= 0.5 && p.varpi <= 1.0))
     return fail("bad gas parameters");
@@ -284,15 +284,8 @@ int esbgk_batch_create(const esbgk_problem* problems, int n, void* d_workspace, 
   for (int i = 0; i < n; ++i) {
     const esbgk_shape& s = problems[i].shape;
     BatchProblem& q = b->bp[i];
-    q.geo.nx = s.nx;
-    q.geo.ny = s.ny;
-    q.geo.nz = s.nz;
-    q.geo.ncells = cells_of(s);
-    q.geo.ncols = ncols_of(s);
-    q.geo.walls = 1;
-    q.geo.nxy = uint32_t(s.nx) * s.ny;
-    q.geo.div_nx = make_fastdiv(s.nx);
-    q.geo.div_ny = make_fastdiv(s.ny);
+    make_geometry(lat->D, lat->Q, uint32_t(s.nx), uint32_t(s.ny), uint32_t(s.nz), true, false, ssize(b->storage),
+                  q.geo);
     q.pop_off = pop;
     q.wp_off = uint32_t(wp);
     pop += size_t(lat->Q) * q.geo.ncells;

@@ -109,6 +109,22 @@ __device__ __forceinline__ void cell_contrib(const CellState<L, C>& s, U* __rest
 
 // ---- kernels ---------------------------------------------------------------
 
+// Thread slot -> cell of the step and reduction kernels: slot t is in-slice
+// index i = t mod ipad of slice s = t / ipad, active when i < inner and
+// s < nslices. ipad is a multiple of 64, so the lanes of a wavefront share
+// their slice, which the kernels use as a scalar.
+struct Slot {
+  uint32_t s, i;
+  bool active;
+};
+
+__device__ __forceinline__ Slot slot_of(uint32_t blk, const Geometry& geo) {
+  const uint32_t wave0 = blk * BLOCK + (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u);
+  const uint32_t s = __builtin_amdgcn_readfirstlane(fdiv(wave0, geo.div_ipad));
+  const uint32_t i = blk * BLOCK + threadIdx.x - s * geo.ipad;
+  return {s, i, s < geo.nslices && i < geo.inner};
+}
+
 // One time step: pull, collide, store, wall partial sums (and, when REDUCE,
 // the FP64 reductions of the pre-collision state).
 template <class L, typename S, bool REDUCE>
@@ -119,29 +135,32 @@ k_step(Geometry geo, const S* __restrict__ src, S* __restrict__ dst, const typen
        int have_prev, double* __restrict__ red_part) {
   using C = typename StepT<S>::type;
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t cell = blk * BLOCK + threadIdx.x;
+  const Slot sl = slot_of(blk, geo);
   double v[NRED];
   if (REDUCE) {
 #pragma unroll
     for (int k = 0; k < NRED; ++k) v[k] = 0.0;
   }
-  if (cell < geo.ncells) {
-    const CellPos p = cell_pos(cell, geo);
-    const PullMode mode = pull_mode<L>(p, geo);
+  if (sl.active) {
+    const CellPos p = slice_pos<L>(sl.s, sl.i, geo);
+    const PullMode mode = pull_mode_wave<L>(sl.s, p, geo);
     C h[L::Q];
-    gather<L, S, C, C>(h, src, geo, cell, p, wp_src, pp, mode);
+    gather_wave<L, S, C, C>(h, src, geo, sl.s, sl.i, p, wp_src, pp, mode);
     CellState<L, C> st;
     collide<L, C>(h, lc, pp, st);
+    const uint32_t bb = geo.sstride * uint32_t(sizeof(S)), pb = geo.pstride * uint32_t(sizeof(S));
+    const Rsrc out = block_rsrc(reinterpret_cast<char*>(dst) + size_t(sl.s) * bb, bb);
 #pragma unroll
-    for (int a = 0; a < L::Q; ++a) st_plane(dst + size_t(a) * geo.ncells, cell * uint32_t(sizeof(S)), narrow<S, C>(h[a]));
+    for (int a = 0; a < L::Q; ++a) buf_st<S>(narrow<S, C>(h[a]), out, sl.i * uint32_t(sizeof(S)), uint32_t(a) * pb);
     if (geo.walls)
       write_wall_partials<L, S, C>([&](int a) { return narrow<S, C>(h[a]); }, p, geo, lc, wp_dst);
-    if (REDUCE) cell_contrib<L, C, C>(st, uprev, cell, geo.ncells, have_prev, v);
+    if (REDUCE) cell_contrib<L, C, C>(st, uprev, sl.s * geo.inner + sl.i, geo.ncells, have_prev, v);
   }
   if (REDUCE) block_reduce_write(v, red_part + size_t(blk) * NRED);
 }
 
-// Reductions of the current level without stepping (FP64 arithmetic).
+// Reductions of the current level without stepping (FP64 arithmetic), over
+// the same slots and workgroups as the fused reductions of the step kernel.
 template <class L, typename S>
 __global__ void __launch_bounds__(BLOCK)
 k_reduce(Geometry geo, const S* __restrict__ src, const typename StepT<S>::type* __restrict__ wp,
@@ -149,20 +168,20 @@ k_reduce(Geometry geo, const S* __restrict__ src, const typename StepT<S>::type*
          typename StepT<S>::type* __restrict__ uprev, int have_prev, double* __restrict__ red_part) {
   using P = typename StepT<S>::type;
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t cell = blk * BLOCK + threadIdx.x;
+  const Slot sl = slot_of(blk, geo);
   double v[NRED];
 #pragma unroll
   for (int k = 0; k < NRED; ++k) v[k] = 0.0;
-  if (cell < geo.ncells) {
-    const CellPos p = cell_pos(cell, geo);
-    const PullMode mode = pull_mode<L>(p, geo);
+  if (sl.active) {
+    const CellPos p = slice_pos<L>(sl.s, sl.i, geo);
+    const PullMode mode = pull_mode_wave<L>(sl.s, p, geo);
     double h[L::Q];
-    gather<L, S, double, P>(h, src, geo, cell, p, wp, pp, mode);
+    gather_wave<L, S, double, P>(h, src, geo, sl.s, sl.i, p, wp, pp, mode);
     RawMoments<L, double> m;
     raw_moments<L, double>(h, lc, false, m);
     CellState<L, double> st;
     reconstruct<L, double>(m, lc, pp, st);
-    cell_contrib<L, double, P>(st, uprev, cell, geo.ncells, have_prev, v);
+    cell_contrib<L, double, P>(st, uprev, sl.s * geo.inner + sl.i, geo.ncells, have_prev, v);
   }
   block_reduce_write(v, red_part + size_t(blk) * NRED);
 }
@@ -199,13 +218,10 @@ k_moments(Geometry geo, const S* __restrict__ src, const typename StepT<S>::type
           uint32_t count, double* __restrict__ out) {
   using P = typename StepT<S>::type;
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
-  const bool act = i < count;
-  const uint32_t cell = c0 + (act ? i : 0u);
-  const CellPos p = cell_pos(cell, geo);
-  const PullMode mode = pull_mode<L>(p, geo);   // inactive lanes repeat cell c0
-  if (!act) return;
+  if (i >= count) return;
+  const CellPos p = cell_pos(c0 + i, geo);
   double h[L::Q];
-  gather<L, S, double, P>(h, src, geo, cell, p, wp, pp, mode);
+  gather_lane<L, S, double, P, size_t>(h, src, geo, p, wp, pp);
   double f[nfields(L::D)];
   cell_fields<L, double>(h, lc, pp, f);
 #pragma unroll
@@ -241,7 +257,7 @@ k_init(Geometry geo, S* __restrict__ dst, double r, const double* __restrict__ r
        const double* __restrict__ T, const double* __restrict__ noise, double amp, uint32_t c0, uint32_t count) {
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= count) return;
-  const uint32_t cell = c0 + i;
+  const size_t elem = cell_elem<L>(cell_pos(c0 + i, geo), geo);
   const double drho = rho ? rho[i] - 1.0 : 0.0;
   double uc[3] = {0.0, 0.0, 0.0};
   if (u) {
@@ -255,7 +271,7 @@ k_init(Geometry geo, S* __restrict__ dst, double r, const double* __restrict__ r
     // rho Shat - 1 = drho Shat + (Shat - 1)
     double hv = drho * (1.0 + sm1) + sm1;
     if (noise) hv += (1.0 + hv) * amp * noise[size_t(a) * count + i];
-    dst[size_t(a) * geo.ncells + cell] = S(hv);
+    dst[size_t(a) * geo.pstride + elem] = S(hv);
   }
 }
 
@@ -272,20 +288,23 @@ k_wall_partials(Geometry geo, const S* __restrict__ src, const LatConsts<typenam
   const uint32_t col = i % geo.ncols;
   const uint32_t sk = i / geo.ncols;       // side * 3 + k
   const int side = int(sk / 3), k = int(sk % 3);
-  const int nw = D == 2 ? int(geo.ny) : int(geo.nz);
+  const int nw = int(geo.nslices);
   const int cw = side == 0 ? k : nw - 1 - k;
-  const uint32_t cell = uint32_t(cw) * geo.ncols + col;   // the wall axis is the slowest
+  const size_t elem = size_t(cw) * geo.sstride + col;   // the wall axis is the slice axis
   const CrossSums<L, S, P> cs =
-      cross_sums<L, S, P>([&](int a) { return src[size_t(a) * geo.ncells + cell]; }, lc);
+      cross_sums<L, S, P>([&](int a) { return src[size_t(a) * geo.pstride + elem]; }, lc);
   wp_dst[sk * geo.ncols + col] = side == 0 ? layer_partial(cs.lo, k) : layer_partial(cs.hi, k);
 }
 
 // ---- launchers -----------------------------------------------------------------
 
+// Workgroups of the step and reduction kernels: nslices * ipad thread slots.
+uint32_t slot_blocks(const Geometry& g) { return uint32_t((uint64_t(g.nslices) * g.ipad + BLOCK - 1) / BLOCK); }
+
 template <class L, typename S>
 static hipError_t step_t(const StepArgs& a) {
   using C = typename StepT<S>::type;
-  const uint32_t nb = (a.geo.ncells + BLOCK - 1) / BLOCK;
+  const uint32_t nb = slot_blocks(a.geo);
   if (a.reduce) {
     hipLaunchKernelGGL((k_step<L, S, true>), dim3(nb), dim3(BLOCK), 0, a.stream, a.geo, static_cast<const S*>(a.src),
                        static_cast<S*>(a.dst), static_cast<const C*>(a.wp_src), static_cast<C*>(a.wp_dst),
@@ -303,7 +322,7 @@ static hipError_t step_t(const StepArgs& a) {
 template <class L, typename S>
 static hipError_t reduce_t(const StepArgs& a) {
   using C = typename StepT<S>::type;
-  const uint32_t nb = (a.geo.ncells + BLOCK - 1) / BLOCK;
+  const uint32_t nb = slot_blocks(a.geo);
   hipLaunchKernelGGL((k_reduce<L, S>), dim3(nb), dim3(BLOCK), 0, a.stream, a.geo, static_cast<const S*>(a.src),
                      static_cast<const C*>(a.wp_src), static_cast<const LatConsts<double>*>(a.lc64),
                      static_cast<const ProbParams<double>*>(a.pp64), static_cast<C*>(a.uprev), a.have_prev,

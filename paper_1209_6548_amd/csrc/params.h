@@ -53,13 +53,28 @@ struct FastDiv {
 };
 
 // Geometry of one lattice (kernel argument, fixed for a handle's life).
+//
+// Cells are grouped in slices along the last axis (y in 2-D, z in 3-D; the
+// wall axis when there are walls): slice s holds the `inner` cells with that
+// last coordinate, numbered i = x (2-D) or i = y nx + x (3-D), and the dense
+// cell index is s * inner + i. Population alpha of cell (s, i) is element
+// s * sstride + alpha * pstride + i of a population buffer: plain SoA is
+// pstride = ncells, sstride = inner; the slice-blocked layout of the
+// single-lattice path is pstride >= inner, sstride >= Q * pstride.
 struct Geometry {
   uint32_t nx, ny, nz;       // extents
   uint32_t ncells;           // nx*ny*nz
-  uint32_t ncols;            // cells of one layer across the wall axis
+  uint32_t ncols;            // cells of one layer across the wall axis (= inner)
   uint32_t walls;            // 1: diffuse walls across the last axis
   uint32_t nxy;              // nx*ny
   FastDiv div_nx, div_ny;    // division by nx and by ny
+  uint32_t inner;            // cells per slice
+  uint32_t nslices;          // slices (ny in 2-D, nz in 3-D)
+  uint32_t pstride;          // elements between the planes of two velocities in a slice
+  uint32_t sstride;          // elements between two consecutive slices
+  uint32_t ipad;             // inner rounded up to a multiple of 64: thread slots per slice
+  FastDiv div_ipad;          // division by ipad
+  uint32_t window_ok;        // 7 slice blocks span < 4 GiB (32-bit offsets of the wave pull)
 };
 
 // Fields per cell returned by the moments kernel: rho, u[D], T, sigma, q[D].

@@ -9,6 +9,10 @@
 // that cross the wall on the next step, from the values as stored; the next
 // step adds the three layers of a column. A population that streams in from
 // beyond a wall takes rho_W(source column) S(T_w, u_w).
+//
+// Addressing follows the slice layout of Geometry: population alpha of the
+// cell (slice s, in-slice index i) is element s sstride + alpha pstride + i.
+// The wall axis, when there are walls, is the slice axis.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,23 +22,6 @@
 namespace esbgk {
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv d) { return (__umulhi(n, d.m) + n) >> d.l; }
-
-// Load / store element boff / sizeof(S) of a velocity plane. The plane base is
-// uniform across the wavefront and boff is a 32-bit byte offset (planes are
-// smaller than 4 GiB), so the access is a scalar-base + vector-offset
-// instruction with no per-lane 64-bit address arithmetic. FP64 populations
-// are stored non-temporally (measured 6% faster for FP64 on MI355X; slower
-// for the narrower types, which keep the default policy).
-template <typename S>
-__device__ __forceinline__ S ld_plane(const S* __restrict__ plane, uint32_t boff) {
-  return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(plane) + boff);
-}
-template <typename S>
-__device__ __forceinline__ void st_plane(S* __restrict__ plane, uint32_t boff, S v) {
-  S* p = reinterpret_cast<S*>(reinterpret_cast<char*>(plane) + boff);
-  if constexpr (sizeof(S) == 8) __builtin_nontemporal_store(v, p);
-  else *p = v;
-}
 
 __device__ __forceinline__ int wrapc(int v, int n) {
   // v in [-3, n + 2], n >= 1
@@ -59,91 +46,188 @@ __device__ __forceinline__ CellPos cell_pos(uint32_t cell, const Geometry& geo) 
   return {int(x), int(y), int(z)};
 }
 
-// At least 3 cells from every edge: no wrap and no wall within reach.
+// Position of in-slice index i of slice s.
 template <class L>
-__device__ __forceinline__ bool interior(const CellPos& p, const Geometry& geo) {
-  bool ok = p.x >= 3 && p.x < int(geo.nx) - 3 && p.y >= 3 && p.y < int(geo.ny) - 3;
-  if (L::D == 3) ok = ok && p.z >= 3 && p.z < int(geo.nz) - 3;
+__device__ __forceinline__ CellPos slice_pos(uint32_t s, uint32_t i, const Geometry& geo) {
+  if (L::D == 2) return {int(i), int(s), 0};
+  const uint32_t y = fdiv(i, geo.div_nx);
+  return {int(i - y * geo.nx), int(y), int(s)};
+}
+
+template <class L>
+__device__ __forceinline__ int slice_of(const CellPos& p) { return L::D == 2 ? p.y : p.z; }
+template <class L>
+__device__ __forceinline__ uint32_t inslice_of(const CellPos& p, const Geometry& geo) {
+  return L::D == 2 ? uint32_t(p.x) : uint32_t(p.y) * geo.nx + uint32_t(p.x);
+}
+// Element offset of a cell within one velocity plane of the layout.
+template <class L>
+__device__ __forceinline__ size_t cell_elem(const CellPos& p, const Geometry& geo) {
+  return size_t(slice_of<L>(p)) * geo.sstride + inslice_of<L>(p, geo);
+}
+
+// At least 3 cells from every in-slice edge (no in-slice wrap within reach).
+template <class L>
+__device__ __forceinline__ bool inslice_interior(const CellPos& p, const Geometry& geo) {
+  bool ok = p.x >= 3 && p.x < int(geo.nx) - 3;
+  if (L::D == 3) ok = ok && p.y >= 3 && p.y < int(geo.ny) - 3;
   return ok;
 }
 
-// At least 3 layers from both walls (always true without walls).
-template <class L>
-__device__ __forceinline__ bool off_walls(const CellPos& p, const Geometry& geo) {
-  if (!geo.walls) return true;
-  const int cw = L::D == 2 ? p.y : p.z;
-  const int nw = L::D == 2 ? int(geo.ny) : int(geo.nz);
-  return cw >= 3 && cw < nw - 3;
+// Ghost value beyond wall `side` for velocity a, from the partial sums of the
+// source column col (Sec. 3.2: rho_W(col) S_alpha(T_w, u_w), deviational).
+template <class L, typename C, typename P>
+__device__ __forceinline__ C wall_ghost(int a, int side, uint32_t col, const Geometry& geo,
+                                        const P* __restrict__ wp, const ProbParams<C>* __restrict__ pp) {
+  const P* q = wp + uint32_t(side) * 3u * geo.ncols + col;
+  const C part = C(q[0]) + C(q[geo.ncols]) + C(q[2u * geo.ncols]);
+  const C drw = (side ? pp->K0[1] : pp->K0[0]) + (side ? pp->invden[1] : pp->invden[0]) * part;
+  const C em1 = side ? pp->Em1[1][a] : pp->Em1[0][a];
+  const C eh = side ? pp->Ehat[1][a] : pp->Ehat[0][a];
+  return em1 + eh * drw;
 }
 
-// How a wavefront pulls: every lane interior (shifted plane bases, no
-// per-velocity arithmetic); some lane at a periodic edge but none near a wall
-// (per-lane wrapped offsets); some lane near a wall (wrapped offsets plus wall
-// ghosts).
-enum PullMode { PULL_FAST = 0, PULL_WRAP = 1, PULL_WALL = 2 };
-
+// In-slice source offsets for shifts -3..3 (periodic in-slice axes).
 template <class L>
-__device__ __forceinline__ PullMode pull_mode(const CellPos& p, const Geometry& geo) {
-  if (__all(interior<L>(p, geo))) return PULL_FAST;
-  return __all(off_walls<L>(p, geo)) ? PULL_WRAP : PULL_WALL;
+__device__ __forceinline__ void inslice_offsets(const CellPos& p, const Geometry& geo, int (&xo)[7], int (&yo)[7]) {
+  const int nx = int(geo.nx), ny = int(geo.ny);
+#pragma unroll
+  for (int k = -3; k <= 3; ++k) {
+    xo[k + 3] = wrapc(p.x - k, nx);
+    yo[k + 3] = L::D == 3 ? wrapc(p.y - k, ny) * nx : 0;
+  }
 }
 
-// Pull the Q populations that stream into cell p. P is the type of the wall
-// partial sums, C the compute type.
+// Raw buffer resource over one slice block: base address, no stride,
+// num_records = the block's bytes (an access beyond it reads zero and writes
+// nothing), 32-bit untyped data.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ Rsrc block_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), short(0), int(bytes), 0x00020000);
+}
+
+// Load / store one storage element at byte voff (per lane) + soff (uniform)
+// of a slice block. FP64 populations are stored non-temporally (measured
+// faster for FP64 on MI355X; slower for the narrower types).
+template <typename S>
+__device__ __forceinline__ S buf_ld(Rsrc r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(S) == 8) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), 0));
+  } else if constexpr (sizeof(S) == 4) {
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0));
+  } else {
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, int(voff), int(soff), 0));
+  }
+}
+template <typename S>
+__device__ __forceinline__ void buf_st(S v, Rsrc r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(S) == 8) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, int(voff), int(soff), 2);
+  } else if constexpr (sizeof(S) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, int(voff), int(soff), 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, int(voff), int(soff), 0);
+  }
+}
+
+// How a wavefront whose lanes share slice s pulls: the seven slices s-3..s+3
+// inside the lattice and every lane far from the in-slice edges (PULL_FAST:
+// one scalar offset per velocity); the seven slices inside but some lane at
+// an in-slice edge (PULL_WRAP: per-lane wrapped in-slice offsets); slice s
+// within 3 of the slice-axis ends (PULL_EDGE: the periodic wrap or the wall
+// ghosts of that axis, one slice block per velocity).
+enum PullMode { PULL_FAST = 0, PULL_WRAP = 1, PULL_EDGE = 2 };
+
+template <class L>
+__device__ __forceinline__ PullMode pull_mode_wave(uint32_t s, const CellPos& p, const Geometry& geo) {
+  const bool s_inner = s >= 3u && s + 3u < geo.nslices && geo.window_ok;
+  if (!s_inner) return PULL_EDGE;
+  return __all(inslice_interior<L>(p, geo)) ? PULL_FAST : PULL_WRAP;
+}
+
+// Pull the Q populations that stream into the cells of a wavefront whose
+// lanes all lie in slice s (s wave-uniform; i = in-slice index of the lane,
+// p its position). In the FAST and WRAP modes one buffer resource spans the
+// slice blocks s-3..s+3 and a velocity's source is a scalar offset (its slice
+// block and plane, less the in-slice shift in FAST mode) plus a per-lane
+// offset. P is the type of the wall partial sums, C the compute type.
 template <class L, typename S, typename C, typename P>
-__device__ __forceinline__ void gather(C (&h)[L::Q], const S* __restrict__ src, const Geometry& geo,
-                                       uint32_t cell, const CellPos& p, const P* __restrict__ wp,
-                                       const ProbParams<C>* __restrict__ pp, PullMode mode) {
+__device__ __forceinline__ void gather_wave(C (&h)[L::Q], const S* __restrict__ src, const Geometry& geo,
+                                            uint32_t s, uint32_t i, const CellPos& p, const P* __restrict__ wp,
+                                            const ProbParams<C>* __restrict__ pp, PullMode mode) {
   constexpr int D = L::D, Q = L::Q;
+  constexpr uint32_t ss = sizeof(S);
+  const uint32_t bb = geo.sstride * ss;         // bytes of one slice block
+  const uint32_t pb = geo.pstride * ss;         // bytes of one velocity plane segment
+  if (mode == PULL_EDGE) {
+    // source slice s - e_s is wave-uniform: a ghost beyond a wall, else one
+    // slice block (wrapped along a periodic slice axis)
+    int xo[7], yo[7];
+    inslice_offsets<L>(p, geo, xo, yo);
+    const int ns = int(geo.nslices);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
+      const uint32_t col = uint32_t(xo[ex + 3] + yo[ey + 3]);
+      int s2 = int(s) - es;
+      if (geo.walls && (s2 < 0 || s2 >= ns)) {
+        h[a] = wall_ghost<L, C, P>(a, s2 < 0 ? 0 : 1, col, geo, wp, pp);
+        continue;
+      }
+      s2 = wrapc(s2, ns);
+      const Rsrc blk = block_rsrc(reinterpret_cast<const char*>(src) + size_t(s2) * bb, bb);
+      h[a] = widen<C, S>(buf_ld<S>(blk, col * ss, uint32_t(a) * pb));
+    }
+    return;
+  }
+  const Rsrc win = block_rsrc(reinterpret_cast<const char*>(src) + size_t(s - 3u) * bb, 7u * bb);
   if (mode == PULL_FAST) {
+    const uint32_t nxb = geo.nx * ss;
+    const uint32_t voff = i * ss;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
-      const long shift = long(ecomp<L>(a, 2)) * long(geo.nxy) + long(ecomp<L>(a, 1)) * long(geo.nx) +
-                         long(ecomp<L>(a, 0));
-      const S* plane = src + size_t(a) * geo.ncells - shift;
-      h[a] = widen<C, S>(ld_plane(plane, cell * uint32_t(sizeof(S))));
+      const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
+      const uint32_t soff = uint32_t(3 - es) * bb + uint32_t(a) * pb - uint32_t(int(ss) * ex) -
+                            (D == 3 ? uint32_t(ey) * nxb : 0u);
+      h[a] = widen<C, S>(buf_ld<S>(win, voff, soff));
     }
     return;
   }
-  // wrapped coordinates of the source for shifts -3..3, pre-scaled to element
-  // offsets; along the wall axis they are left unwrapped (out of range = beyond
-  // a wall)
-  const int nx = int(geo.nx), ny = int(geo.ny), nz = int(geo.nz);
-  const bool walls = geo.walls != 0;
-  int xo[7], yo[7], zo[7];
-#pragma unroll
-  for (int s = -3; s <= 3; ++s) {
-    xo[s + 3] = wrapc(p.x - s, nx);
-    yo[s + 3] = ((D == 2 && walls) ? p.y - s : wrapc(p.y - s, ny)) * nx;
-    zo[s + 3] = (D == 3) ? ((walls ? p.z - s : wrapc(p.z - s, nz)) * int(geo.nxy)) : 0;
-  }
-  if (mode == PULL_WRAP) {
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const uint32_t off = uint32_t(xo[ecomp<L>(a, 0) + 3] + yo[ecomp<L>(a, 1) + 3] + zo[ecomp<L>(a, 2) + 3]);
-      h[a] = widen<C, S>(ld_plane(src + size_t(a) * geo.ncells, off * uint32_t(sizeof(S))));
-    }
-    return;
-  }
-  const int cw = D == 2 ? p.y : p.z;
-  const int nw = D == 2 ? ny : nz;
+  int xo[7], yo[7];
+  inslice_offsets<L>(p, geo, xo, yo);
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
-    const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), ez = ecomp<L>(a, 2);
-    const int sw = cw - (D == 2 ? ey : ez);
-    if (walls && (sw < 0 || sw >= nw)) {
-      const int side = sw < 0 ? 0 : 1;
-      const uint32_t col = uint32_t(xo[ex + 3] + (D == 2 ? 0 : yo[ey + 3]));
-      const P* q = wp + uint32_t(side) * 3u * geo.ncols + col;
-      const C part = C(q[0]) + C(q[geo.ncols]) + C(q[2u * geo.ncols]);
-      const C drw = (side ? pp->K0[1] : pp->K0[0]) + (side ? pp->invden[1] : pp->invden[0]) * part;
-      const C em1 = side ? pp->Em1[1][a] : pp->Em1[0][a];
-      const C eh = side ? pp->Ehat[1][a] : pp->Ehat[0][a];
-      h[a] = em1 + eh * drw;
-    } else {
-      const uint32_t off = uint32_t(xo[ex + 3] + yo[ey + 3] + zo[ez + 3]);
-      h[a] = widen<C, S>(ld_plane(src + size_t(a) * geo.ncells, off * uint32_t(sizeof(S))));
+    const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
+    const uint32_t off = uint32_t(xo[ex + 3] + yo[ey + 3]) * ss;
+    h[a] = widen<C, S>(buf_ld<S>(win, off, uint32_t(3 - es) * bb + uint32_t(a) * pb));
+  }
+}
+
+// Pull for a lane at an arbitrary cell (no wavefront structure assumed).
+// OffT is the element-offset type: 32-bit for buffers below 4 GiB.
+template <class L, typename S, typename C, typename P, typename OffT>
+__device__ __forceinline__ void gather_lane(C (&h)[L::Q], const S* __restrict__ src, const Geometry& geo,
+                                            const CellPos& p, const P* __restrict__ wp,
+                                            const ProbParams<C>* __restrict__ pp) {
+  constexpr int D = L::D, Q = L::Q;
+  int xo[7], yo[7];
+  inslice_offsets<L>(p, geo, xo, yo);
+  const int ns = int(geo.nslices), s = slice_of<L>(p);
+  const bool walls = geo.walls != 0;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
+    const uint32_t off = uint32_t(xo[ex + 3] + yo[ey + 3]);
+    int s2 = s - es;
+    if (walls && (s2 < 0 || s2 >= ns)) {
+      h[a] = wall_ghost<L, C, P>(a, s2 < 0 ? 0 : 1, off, geo, wp, pp);
+      continue;
     }
+    if (!walls) s2 = wrapc(s2, ns);
+    const OffT e = OffT(s2) * OffT(geo.sstride) + OffT(a) * OffT(geo.pstride) + OffT(off);
+    h[a] = widen<C, S>(src[e]);
   }
 }
 
@@ -185,12 +269,11 @@ __device__ __forceinline__ P layer_partial(const P (&g)[3], int k) {
 template <class L, typename S, typename P, typename GetS>
 __device__ __forceinline__ void write_wall_partials(GetS stored, const CellPos& p, const Geometry& geo,
                                                     const LatConsts<P>* __restrict__ lw, P* __restrict__ wp_dst) {
-  constexpr int D = L::D;
-  const int cw = D == 2 ? p.y : p.z;
-  const int nw = D == 2 ? int(geo.ny) : int(geo.nz);
+  const int cw = slice_of<L>(p);
+  const int nw = int(geo.nslices);
   if (!(cw < 3 || cw >= nw - 3)) return;
   const CrossSums<L, S, P> cs = cross_sums<L, S, P>(stored, lw);
-  const uint32_t col = D == 2 ? uint32_t(p.x) : uint32_t(p.y) * geo.nx + uint32_t(p.x);
+  const uint32_t col = inslice_of<L>(p, geo);
   if (cw < 3) wp_dst[uint32_t(cw) * geo.ncols + col] = layer_partial(cs.lo, cw);
   if (cw >= nw - 3) {
     const int k = nw - 1 - cw;

@@ -346,4 +346,38 @@ FastDiv make_fastdiv(uint32_t d) {
   return f;
 }
 
+bool make_geometry(int D, int Q, uint32_t nx, uint32_t ny, uint32_t nz, bool walls, bool sliced, size_t ss,
+                   Geometry& g) {
+  g = Geometry{};
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  const uint64_t n = uint64_t(nx) * ny * nz;
+  if (n >= (uint64_t(1) << 31)) return false;
+  g.ncells = uint32_t(n);
+  g.nxy = nx * ny;
+  g.walls = walls ? 1u : 0u;
+  g.div_nx = make_fastdiv(nx);
+  g.div_ny = make_fastdiv(ny);
+  g.inner = D == 2 ? nx : nx * ny;
+  g.nslices = D == 2 ? ny : nz;
+  g.ncols = g.inner;
+  const uint64_t ipad = (uint64_t(g.inner) + 63) / 64 * 64;
+  if (uint64_t(g.nslices) * ipad >= (uint64_t(1) << 31)) return false;
+  g.ipad = uint32_t(ipad);
+  g.div_ipad = make_fastdiv(g.ipad);
+  if (sliced) {
+    const uint64_t ps = ipad;
+    const uint64_t sst = uint64_t(Q) * ps + SLICE_PAD;
+    if (sst * ss >= (uint64_t(1) << 32)) return false;
+    g.pstride = uint32_t(ps);
+    g.sstride = uint32_t(sst);
+    g.window_ok = 7 * sst * ss < (uint64_t(1) << 32) ? 1u : 0u;
+  } else {
+    g.pstride = g.ncells;
+    g.sstride = g.inner;
+  }
+  return true;
+}
+
 }  // namespace esbgk

@@ -42,4 +42,14 @@ void pack_lattice(const HostLattice& lat, LatConsts<C>& d);
 
 FastDiv make_fastdiv(uint32_t d);
 
+// Geometry of an nx x ny x nz lattice of Q velocities (D = 2: nz = 1) stored
+// in elements of ss bytes. sliced: the slice-blocked population layout of the
+// single-lattice path, pstride = ipad and sstride = Q ipad + SLICE_PAD;
+// otherwise plain SoA. Returns false if the slot count or a slice block's
+// byte size does not fit 32 bits.
+constexpr uint32_t SLICE_PAD = 256;   // elements between consecutive slice blocks
+bool make_geometry(int D, int Q, uint32_t nx, uint32_t ny, uint32_t nz, bool walls, bool sliced, size_t ss,
+                   Geometry& g);
+
+
 }  // namespace esbgk
