@@ -147,10 +147,24 @@ def measured_traffic(storage):
         return None
 
 
-def cpu_baseline(r, budget_s=20.0):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(r, budget_s=20.0, one_core_s=8.0):
     """The FP64 oracle on a bounded sample of the same workload: the 1024 x
     1024 channel's per-cell work (D2Q37, walls, force, N = 4) on a 256 x 256
-    instance with the same Kn, Pr and walls, stepped until the time budget."""
+    instance with the same Kn, Pr and walls, stepped until the time budget;
+    then again on one core (BLAS limited to one thread) for a shorter budget."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
     from oracle import lattice as OL
     from oracle import quadrature
     from paper_1209_6548_amd import workloads
@@ -159,23 +173,30 @@ def cpu_baseline(r, budget_s=20.0):
     prob = OL.Problem(vs, cfg["dims"], Kn=cfg["Kn"], Pr=cfg["Pr"], varpi=cfg["varpi"], walls=True,
                       wall_lo=OL.Wall(cfg["T_w"][0]), wall_hi=OL.Wall(cfg["T_w"][1]), g=cfg["g"])
     M = prob.M
-    f = OL.equilibrium_state(prob, np.ones(M), np.zeros((M, 2)), np.ones(M))
-    f = OL.step(f, prob)
-    t0 = time.perf_counter()
-    n = 0
-    while time.perf_counter() - t0 < budget_s and n < 200:
+
+    def timed(budget):
+        f = OL.equilibrium_state(prob, np.ones(M), np.zeros((M, 2)), np.ones(M))
         f = OL.step(f, prob)
-        n += 1
-    dt = time.perf_counter() - t0
-    threads = 1
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < budget and n < 200:
+            f = OL.step(f, prob)
+            n += 1
+        return n, time.perf_counter() - t0
+
+    n, dt = timed(budget_s)
+    threads = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
+    with threadpool_limits(limits=1):
+        n1, dt1 = timed(one_core_s)
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
-    except Exception:
-        pass
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
     return dict(value=M * n / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
-                sample=f"256x256 D2Q37 channel (same Kn, Pr, walls, force as the 1024x1024 case), {n} steps, "
-                       f"{dt:.1f} s; cores = BLAS threads available to numpy")
+                sample=f"256x256 D2Q37 channel (same Kn, Pr, walls, force as the 1024x1024 case), {n} steps in "
+                       f"{dt:.1f} s with numpy on {threads} BLAS threads",
+                one_core=dict(value=M * n1 / dt1 / 1e6, steps=n1, seconds=round(dt1, 2)),
+                host=dict(cpu_model=_cpu_model(), cores_available=avail))
 
 
 def main():
