@@ -22,14 +22,23 @@ integer e_alpha permits exactly):
   with (omega, phi) = (dt/tau, 1) for Euler and (2x/(2+x), 1 - omega/2),
   x = dt/tau, for the trapezoidal rule, where f_ES and F are built from the
   moments of the physical f recovered from fbar (``physical_state``).
-* Walls (Sec. 3.2, Maxwell model with full accommodation): flat walls lie
-  half a cell outside the first and last layer along the wall axis (the last
-  spatial axis). Every population that streams across a wall in one step is
-  re-emitted as rho_W S(T_W, u_W): the ghost cells beyond the wall carry
-  rho_W E_alpha, E = S(T_W, u_W) of eq. feq0 truncated at the bulk order N,
-  with rho_W per wall-parallel column fixed by the flux balance of Sec. 3.2
-  where |xi . n| becomes the number of layers |e_n| that velocity crosses in
-  one step.
+* Walls (Sec. 3.2): flat walls lie half a cell outside the first and last
+  layer along the wall axis (the last spatial axis). With full accommodation
+  (the paper's choice), every population that streams across a wall in one
+  step is re-emitted as rho_W S(T_W, u_W): the ghost cells beyond the wall
+  carry rho_W E_alpha, E = S(T_W, u_W) of eq. feq0 truncated at the bulk
+  order N, with rho_W per wall-parallel column fixed by the flux balance of
+  Sec. 3.2 where |xi . n| becomes the number of layers |e_n| that velocity
+  crosses in one step.
+* Maxwell's model (Sec. 3.2): a fraction gamma of the particles that hit a
+  wall is re-emitted diffusely and 1 - gamma is reflected specularly. On the
+  lattice a population alpha pulled from beyond the low wall (source layer
+  t - e_n < 0) is gamma rho_W E_alpha + (1 - gamma) f_alpha'(column, layer
+  e_n - 1 - t), alpha' the velocity with e_n negated: the particle that left
+  that layer towards the wall, mirrored in the plane half a cell below layer
+  0; likewise at the high wall with the plane half a cell above layer
+  n - 1. rho_W keeps its definition, so the diffuse part returns the
+  fraction gamma of the flux that crossed and the specular part the rest.
 """
 
 from dataclasses import dataclass, field
@@ -43,6 +52,7 @@ from . import model
 class Wall:
     T: float = 1.0
     u: tuple = (0.0, 0.0, 0.0)
+    gamma: float = 1.0      # accommodation: fraction re-emitted diffusely (Sec. 3.2)
 
 
 @dataclass
@@ -88,11 +98,18 @@ class Problem:
         if self.walls:
             self.E_lo = self._wall_populations(self.wall_lo)
             self.E_hi = self._wall_populations(self.wall_hi)
+            e = vs.e
+            flipped = e.copy()
+            flipped[:, -1] = -flipped[:, -1]
+            lookup = {tuple(v): k for k, v in enumerate(e)}
+            self.mirror = np.array([lookup[tuple(v)] for v in flipped])
 
     def _wall_populations(self, wall):
         u = np.asarray(wall.u[: self.D], dtype=np.float64)
         if u[-1] != 0.0:
             raise ValueError("wall velocity must be tangential")
+        if not 0.0 <= wall.gamma <= 1.0:
+            raise ValueError("accommodation must lie in [0, 1]")
         E = model.truncated_maxwellian(np.ones(1), u[None, :], np.array([wall.T]),
                                        self.vs.c, self.vs.w, self.N)
         return E[:, 0]
@@ -196,8 +213,19 @@ def gather(f, prob, cells=None):
         hi = idx == -2
         Elo = np.broadcast_to(prob.E_lo[:, None], idx.shape)
         Ehi = np.broadcast_to(prob.E_hi[:, None], idx.shape)
-        out[lo] = rw_lo[col[lo]] * Elo[lo]
-        out[hi] = rw_hi[col[hi]] * Ehi[hi]
+        out[lo] = prob.wall_lo.gamma * rw_lo[col[lo]] * Elo[lo]
+        out[hi] = prob.wall_hi.gamma * rw_hi[col[hi]] * Ehi[hi]
+        # specular part: alpha' = mirror(alpha) from the mirrored layer
+        nW = prob.dims[-1]
+        t = prob.coords[cells][:, -1][None, :]                      # target layer (1, K)
+        e_n = prob.vs.e[:, -1][:, None]                            # (Q, 1)
+        mir = np.broadcast_to(prob.mirror[:, None], idx.shape)
+        for mask, layer, gam in ((lo, e_n - 1 - t, prob.wall_lo.gamma),
+                                 (hi, 2 * nW - 1 - (t - e_n), prob.wall_hi.gamma)):
+            if gam == 1.0 or not mask.any():
+                continue
+            src = col + np.broadcast_to(layer, idx.shape) * prob.ncols
+            out[mask] += (1.0 - gam) * f[mir[mask], src[mask]]
     return out
 
 
