@@ -118,6 +118,17 @@ int esbgk_set_gas(esbgk_ctx* ctx, double Kn, double Pr, double varpi);
  * E_INVALID if the lattice has no walls. */
 int esbgk_set_wall(esbgk_ctx* ctx, int side, double T_w, const double u_w[3]);
 
+/* Maxwell's wall model (Sec. 3.2): accommodation 0 <= gamma <= 1 of wall
+ * `side`, the fraction of the particles reaching it that is re-emitted
+ * diffusely (as set by esbgk_set_wall); 1 - gamma is reflected specularly.
+ * A population pulled from beyond the wall becomes gamma times the diffuse
+ * ghost plus 1 - gamma times its specular image: the mirror velocity (wall-
+ * normal component negated) leaving the mirrored layer of the same source
+ * column. rho_W keeps its definition, so mass is conserved for every gamma.
+ * Default 1 (the paper's full accommodation). E_INVALID if the lattice has no
+ * walls or gamma is outside [0, 1]. */
+int esbgk_set_wall_accommodation(esbgk_ctx* ctx, int side, double gamma);
+
 /* Body force g[3] (eq. esbgk, its Hermite expansion in Sec. 2.2). */
 int esbgk_set_body_force(esbgk_ctx* ctx, const double g[3]);
 
@@ -191,6 +202,9 @@ typedef struct {
   double Kn, Pr, varpi;
   double T_w[2], u_w[2][3];   /* low / high wall */
   double g[3];
+  double specular[2];         /* 1 - gamma of the low / high wall (0 = fully
+                                 diffuse, the paper's walls; see
+                                 esbgk_set_wall_accommodation) */
 } esbgk_problem;
 
 size_t esbgk_batch_workspace_bytes(const esbgk_problem* problems, int n);

@@ -39,7 +39,8 @@ class Shape(ctypes.Structure):
 
 class Problem(ctypes.Structure):
     _fields_ = [("shape", Shape), ("Kn", ctypes.c_double), ("Pr", ctypes.c_double), ("varpi", ctypes.c_double),
-                ("T_w", ctypes.c_double * 2), ("u_w", (ctypes.c_double * 3) * 2), ("g", ctypes.c_double * 3)]
+                ("T_w", ctypes.c_double * 2), ("u_w", (ctypes.c_double * 3) * 2), ("g", ctypes.c_double * 3),
+                ("specular", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -67,6 +68,7 @@ def lib():
             "esbgk_destroy": (I, [P]),
             "esbgk_set_gas": (I, [P, D, D, D]),
             "esbgk_set_wall": (I, [P, I, D, DP]),
+            "esbgk_set_wall_accommodation": (I, [P, I, D]),
             "esbgk_set_body_force": (I, [P, DP]),
             "esbgk_init_equilibrium": (I, [P, DP, DP, DP, DP, D]),
             "esbgk_set_populations": (I, [P, DP]),
@@ -204,6 +206,11 @@ class Lattice:
         uu[:len(u)] = u
         self._check(lib().esbgk_set_wall(self._ctx, int(side), float(T), _dp(uu)), "set_wall")
 
+    def set_accommodation(self, side, gamma):
+        """Maxwell's wall model: fraction gamma of wall `side` re-emitted
+        diffusely, 1 - gamma reflected specularly (default 1)."""
+        self._check(lib().esbgk_set_wall_accommodation(self._ctx, int(side), float(gamma)), "set_accommodation")
+
     def set_body_force(self, g):
         gg = np.zeros(3)
         gg[:len(g)] = g
@@ -275,7 +282,7 @@ class Lattice:
 
 
 def make_problem(velset, nx, ny, nz=1, storage="f32", scheme="trapezoid", n_ref=0, Kn=0.1, Pr=1.0, varpi=0.5,
-                 T_w=(1.0, 1.0), u_w=((0, 0, 0), (0, 0, 0)), g=(0, 0, 0)):
+                 T_w=(1.0, 1.0), u_w=((0, 0, 0), (0, 0, 0)), g=(0, 0, 0), accommodation=(1.0, 1.0)):
     p = Problem()
     p.shape = Shape(_VELSET[velset], nx, ny, nz, 1, _STORAGE[storage], _SCHEME[scheme], n_ref)
     p.Kn, p.Pr, p.varpi = Kn, Pr, varpi
@@ -285,6 +292,8 @@ def make_problem(velset, nx, ny, nz=1, storage="f32", scheme="trapezoid", n_ref=
             p.u_w[s][i] = u_w[s][i] if i < len(u_w[s]) else 0.0
     for i in range(3):
         p.g[i] = g[i] if i < len(g) else 0.0
+    for s in range(2):
+        p.specular[s] = 1.0 - accommodation[s]
     return p
 
 

@@ -123,6 +123,7 @@ struct esbgk_ctx {
   double Kn = 0.1, Pr = 1.0, varpi = 0.5;
   double Tw[2] = {1.0, 1.0};
   double uw[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  double gam[2] = {1.0, 1.0};     // wall accommodation (Maxwell's model)
   double g[3] = {0, 0, 0};
   int n_ref = 0;
   // host copies of the device parameter blocks
@@ -227,7 +228,8 @@ int build_graph(esbgk_ctx* c, int parity) {
 }
 
 int upload_params(esbgk_ctx* c) {
-  const HostProblem hp = make_problem(*c->lat, c->n_ref, c->shape.scheme, c->Kn, c->Pr, c->varpi, c->g, c->Tw, c->uw);
+  const HostProblem hp =
+      make_problem(*c->lat, c->n_ref, c->shape.scheme, c->Kn, c->Pr, c->varpi, c->g, c->Tw, c->uw, c->gam);
   pack_params<double>(hp, c->lat->Q, c->pp64);
   HIP_OR_FAIL(c, hipMemcpyAsync(c->at(c->lay.pp64), &c->pp64, sizeof(c->pp64), hipMemcpyHostToDevice, c->stream),
               "upload parameters");
@@ -398,6 +400,15 @@ int esbgk_set_wall(esbgk_ctx* c, int side, double T_w, const double u_w[3]) {
     if (!std::isfinite(u_w[i])) return set_err(c, ESBGK_E_INVALID, "u_w must be finite");
   c->Tw[side] = T_w;
   for (int i = 0; i < 3; ++i) c->uw[side][i] = i < c->lat->D ? u_w[i] : 0.0;
+  return upload_params(c);
+}
+
+int esbgk_set_wall_accommodation(esbgk_ctx* c, int side, double gamma) {
+  CHECK_CTX(c);
+  if (!c->shape.walls) return set_err(c, ESBGK_E_INVALID, "lattice has no walls");
+  if (side != 0 && side != 1) return set_err(c, ESBGK_E_INVALID, "side must be 0 or 1");
+  if (!(gamma >= 0.0 && gamma <= 1.0)) return set_err(c, ESBGK_E_INVALID, "gamma must lie in [0, 1]");
+  c->gam[side] = gamma;
   return upload_params(c);
 }
 

@@ -53,6 +53,7 @@ bool valid_problem(const esbgk_problem& p, const esbgk_problem& first, std::stri
   const int W = s.velset == ESBGK_D2Q37 ? 1 : 2;   // wall-normal axis
   for (int side = 0; side < 2; ++side) {
     if (!(p.T_w[side] > 0.0)) return fail("T_w must be > 0");
+    if (!(p.specular[side] >= 0.0 && p.specular[side] <= 1.0)) return fail("specular must lie in [0, 1]");
     if (p.u_w[side][W] != 0.0) return fail("wall velocity must be tangential");
   }
   return true;
@@ -292,8 +293,9 @@ int esbgk_batch_create(const esbgk_problem* problems, int n, void* d_workspace, 
     pop = (pop + 63) / 64 * 64;
     wp += 6 * size_t(q.geo.ncols);
     const int nref = s.n_ref > 0 ? s.n_ref : (lat->D == 2 ? s.ny : s.nz);
+    const double gam[2] = {1.0 - problems[i].specular[0], 1.0 - problems[i].specular[1]};
     const HostProblem hp = make_problem(*lat, nref, s.scheme, problems[i].Kn, problems[i].Pr, problems[i].varpi,
-                                        problems[i].g, problems[i].T_w, problems[i].u_w);
+                                        problems[i].g, problems[i].T_w, problems[i].u_w, gam);
     pack_params<double>(hp, lat->Q, pps64[i]);
     if (csize(b->storage) == 8) pack_params<double>(hp, lat->Q, *reinterpret_cast<ProbParams<double>*>(&pps[i * ppsz]));
     else pack_params<float>(hp, lat->Q, *reinterpret_cast<ProbParams<float>*>(&pps[i * ppsz]));

@@ -54,4 +54,26 @@ __host__ __device__ constexpr int ecomp(int alpha, int a) {
   return alpha == 0 ? 0 : (alpha <= L::P ? L::E[alpha - 1][a] : -L::E[alpha - 1 - L::P][a]);
 }
 
+// The velocity whose last component (the wall normal) is that of alpha
+// negated and whose other components are alpha's: the specular image at a
+// wall across the last axis.
+template <class L>
+__host__ __device__ constexpr int mirror(int alpha) {
+  for (int b = 0; b < L::Q; ++b) {
+    bool same = ecomp<L>(b, L::D - 1) == -ecomp<L>(alpha, L::D - 1);
+    for (int k = 0; k < L::D - 1; ++k) same = same && ecomp<L>(b, k) == ecomp<L>(alpha, k);
+    if (same) return b;
+  }
+  return -1;
+}
+
+template <class L>
+constexpr bool mirror_is_an_involution() {
+  for (int a = 0; a < L::Q; ++a)
+    if (mirror<L>(a) < 0 || mirror<L>(mirror<L>(a)) != a) return false;
+  return true;
+}
+static_assert(mirror_is_an_involution<D2Q37>() && mirror_is_an_involution<D3Q39>(),
+              "every velocity needs a mirror image in the set");
+
 }  // namespace esbgk

@@ -36,6 +36,10 @@ struct LatConsts {
 //   invden  1/den, den = sum_{alpha entering} |e_n| w_alpha Ehat_alpha
 // so that rho_W - 1 = K0 + invden * (sum of the partial sums of w h over the
 // populations that leave through the wall).
+//   gam       accommodation gamma of each wall (Maxwell's model, Sec. 3.2):
+//             the fraction re-emitted diffusely; 1 - gamma is reflected
+//             specularly
+//   specular  some wall has gamma < 1
 template <typename C>
 struct ProbParams {
   C dt, hs, hsdt, xcoef, omv, invPr, b;
@@ -44,6 +48,8 @@ struct ProbParams {
   C Em1[2][QMAX];
   C Ehat[2][QMAX];
   C K0[2], invden[2];
+  C gam[2];
+  int specular;
 };
 
 // Division by a run-time constant d for n < 2^31: q = (umulhi(n, m) + n) >> l

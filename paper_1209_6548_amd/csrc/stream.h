@@ -87,6 +87,24 @@ __device__ __forceinline__ C wall_ghost(int a, int side, uint32_t col, const Geo
   return em1 + eh * drw;
 }
 
+// Population alpha pulled from beyond wall `side` (Sec. 3.2, Maxwell's
+// model): gamma times the diffuse ghost plus 1 - gamma times the specular
+// image, velocity mirror(alpha) leaving the mirrored layer of the same source
+// column (a particle that flew into the wall, reflected in its plane).
+// image() loads that stored value; it is not called for fully diffuse walls.
+template <class L, typename C, typename P, typename Image>
+__device__ __forceinline__ C wall_pull(int a, int side, uint32_t col, const Geometry& geo, const P* __restrict__ wp,
+                                       const ProbParams<C>* __restrict__ pp, Image image) {
+  const C hd = wall_ghost<L, C, P>(a, side, col, geo, wp, pp);
+  if (!pp->specular) return hd;
+  const C gam = side ? pp->gam[1] : pp->gam[0];
+  return gam * hd + (C(1) - gam) * image();
+}
+
+// Layer of the specular image of a pull from slice s2 beyond a wall (the
+// reflection in the plane half a cell outside the first or last layer).
+__device__ __forceinline__ int mirror_layer(int s2, int ns) { return s2 < 0 ? -1 - s2 : 2 * ns - 1 - s2; }
+
 // In-slice source offsets for shifts -3..3 (periodic in-slice axes).
 template <class L>
 __device__ __forceinline__ void inslice_offsets(const CellPos& p, const Geometry& geo, int (&xo)[7], int (&yo)[7]) {
@@ -173,7 +191,11 @@ __device__ __forceinline__ void gather_wave(C (&h)[L::Q], const S* __restrict__ 
       const uint32_t col = uint32_t(xo[ex + 3] + yo[ey + 3]);
       int s2 = int(s) - es;
       if (geo.walls && (s2 < 0 || s2 >= ns)) {
-        h[a] = wall_ghost<L, C, P>(a, s2 < 0 ? 0 : 1, col, geo, wp, pp);
+        const int m = mirror_layer(s2, ns);
+        h[a] = wall_pull<L, C, P>(a, s2 < 0 ? 0 : 1, col, geo, wp, pp, [&]() {
+          const Rsrc img = block_rsrc(reinterpret_cast<const char*>(src) + size_t(m) * bb, bb);
+          return widen<C, S>(buf_ld<S>(img, col * ss, uint32_t(mirror<L>(a)) * pb));
+        });
         continue;
       }
       s2 = wrapc(s2, ns);
@@ -222,7 +244,11 @@ __device__ __forceinline__ void gather_lane(C (&h)[L::Q], const S* __restrict__ 
     const uint32_t off = uint32_t(xo[ex + 3] + yo[ey + 3]);
     int s2 = s - es;
     if (walls && (s2 < 0 || s2 >= ns)) {
-      h[a] = wall_ghost<L, C, P>(a, s2 < 0 ? 0 : 1, off, geo, wp, pp);
+      const int m = mirror_layer(s2, ns);
+      h[a] = wall_pull<L, C, P>(a, s2 < 0 ? 0 : 1, off, geo, wp, pp, [&]() {
+        const OffT e = OffT(m) * OffT(geo.sstride) + OffT(mirror<L>(a)) * OffT(geo.pstride) + OffT(off);
+        return widen<C, S>(src[e]);
+      });
       continue;
     }
     if (!walls) s2 = wrapc(s2, ns);

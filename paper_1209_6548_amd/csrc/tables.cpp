@@ -269,7 +269,7 @@ double shat_minus_one(const HostLattice& lat, int a, double T, const double u[3]
 }
 
 HostProblem make_problem(const HostLattice& lat, int n_ref, int scheme, double Kn, double Pr, double varpi,
-                         const double g[3], const double Tw[2], const double uw[2][3]) {
+                         const double g[3], const double Tw[2], const double uw[2][3], const double gam[2]) {
   HostProblem p{};
   const double dx = 1.0 / double(n_ref);
   p.dt = dx / lat.r;
@@ -299,7 +299,9 @@ HostProblem make_problem(const HostLattice& lat, int n_ref, int scheme, double K
     }
     p.K0[side] = leave / den - 1.0;
     p.invden[side] = 1.0 / den;
+    p.gam[side] = gam[side];
   }
+  p.specular = (gam[0] < 1.0 || gam[1] < 1.0) ? 1 : 0;
   return p;
 }
 
@@ -322,7 +324,9 @@ void pack_params(const HostProblem& h, int Q, ProbParams<C>& d) {
     }
     d.K0[s] = C(h.K0[s]);
     d.invden[s] = C(h.invden[s]);
+    d.gam[s] = C(h.gam[s]);
   }
+  d.specular = h.specular;
 }
 
 template <typename C>

@@ -30,10 +30,12 @@ struct HostProblem {
   double Em1[2][QMAX];
   double Ehat[2][QMAX];
   double K0[2], invden[2];
+  double gam[2];
+  int specular;
 };
 
 HostProblem make_problem(const HostLattice& lat, int n_ref, int scheme, double Kn, double Pr, double varpi,
-                         const double g[3], const double Tw[2], const double uw[2][3]);
+                         const double g[3], const double Tw[2], const double uw[2][3], const double gam[2]);
 
 template <typename C>
 void pack_params(const HostProblem& h, int Q, ProbParams<C>& d);

@@ -36,8 +36,9 @@ def oracle_problem(cfg, scheme="trapezoid"):
     kw = dict(Kn=cfg["Kn"], Pr=cfg["Pr"], varpi=cfg.get("varpi", 0.5), walls=cfg.get("walls", False),
               g=tuple(cfg.get("g", (0, 0, 0))), scheme=scheme, n_ref=cfg.get("n_ref", 0))
     if kw["walls"]:
-        kw["wall_lo"] = OL.Wall(cfg["T_w"][0], tuple(cfg["u_w"][0]))
-        kw["wall_hi"] = OL.Wall(cfg["T_w"][1], tuple(cfg["u_w"][1]))
+        gam = cfg.get("gamma", (1.0, 1.0))
+        kw["wall_lo"] = OL.Wall(cfg["T_w"][0], tuple(cfg["u_w"][0]), gam[0])
+        kw["wall_hi"] = OL.Wall(cfg["T_w"][1], tuple(cfg["u_w"][1]), gam[1])
     return OL.Problem(vs, tuple(cfg["dims"]), **kw)
 
 
@@ -50,6 +51,9 @@ def gpu_lattice(cfg, storage=None, scheme="trapezoid"):
     if cfg.get("walls", False):
         lat.set_wall(0, cfg["T_w"][0], cfg["u_w"][0])
         lat.set_wall(1, cfg["T_w"][1], cfg["u_w"][1])
+        if "gamma" in cfg:
+            lat.set_accommodation(0, cfg["gamma"][0])
+            lat.set_accommodation(1, cfg["gamma"][1])
     lat.set_body_force(cfg.get("g", (0, 0, 0)))
     return lat
 

@@ -70,6 +70,25 @@ def test_step_parity(velset, dims, walls, storage):
         assert np.abs(h - ho).max() / np.abs(ho).max() < 1e-12
 
 
+WALL_CASES = [c for c in CASES if c[2]]
+
+
+@pytest.mark.parametrize("velset,dims,walls", WALL_CASES)
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_partial_accommodation_parity(velset, dims, walls, storage):
+    """Maxwell's wall model (Sec. 3.2): a specular low wall and a partly
+    accommodating high wall, moving and at different temperatures."""
+    cfg = dict(H.small_cfg(velset, dims, walls), gamma=(0.0, 0.6))
+    lat, prob, f = _run_pair(cfg, storage, 12)
+    ea, er = H.assert_parity(lat.read_moments(), H.oracle_fields(f, prob), storage)
+    print(f"{velset} {dims} gamma=(0, 0.6) {storage}: scale-rel {max(ea.values()):.2e} "
+          f"signal-rel {max(er.values()):.2e}")
+    if storage == "f64":
+        h = lat.get_populations()
+        ho = OL.to_deviation(f, prob)
+        assert np.abs(h - ho).max() / np.abs(ho).max() < 1e-12
+
+
 @pytest.mark.parametrize("velset,dims,walls", [CASES[1], CASES[5]])
 def test_euler_scheme_parity(velset, dims, walls):
     cfg = H.small_cfg(velset, dims, walls, Kn=0.2)
@@ -244,6 +263,26 @@ def test_batch_matches_oracle_per_problem():
         H.assert_parity(b.read_moments(i), H.oracle_fields(f, prob), "f64")
 
 
+def test_batch_accommodation_matches_oracle():
+    from paper_1209_6548_amd import Batch, make_problem
+    gammas = ((0.0, 0.0), (0.5, 1.0), (1.0, 0.25))
+    cfgs = [dict(H.small_cfg("D2Q37", (4, ny), True, Kn=kn), gamma=gam) for (ny, kn), gam in
+            zip(((16, 0.05), (23, 0.2), (9, 0.1)), gammas)]
+    probs = [make_problem("D2Q37", c["dims"][0], c["dims"][1], 1, storage="f64", Kn=c["Kn"], Pr=c["Pr"],
+                          varpi=c["varpi"], T_w=c["T_w"], u_w=c["u_w"], g=c["g"], accommodation=c["gamma"])
+             for c in cfgs]
+    b = Batch(probs)
+    b.set_layout(64, 2)
+    b.init_equilibrium()
+    steps = 15
+    b.step(steps)
+    for i, c in enumerate(cfgs):
+        prob = H.oracle_problem(c)
+        f = OL.equilibrium_state(prob, np.ones(prob.M), np.zeros((prob.M, 2)), np.ones(prob.M))
+        f = OL.run(f, prob, steps)
+        H.assert_parity(b.read_moments(i), H.oracle_fields(f, prob), "f64")
+
+
 def test_batch_fp32_layouts_agree():
     from paper_1209_6548_amd import Batch, lattice_info, workloads, make_problem
     r = lattice_info("D2Q37")["r"]
@@ -274,6 +313,13 @@ def test_invalid_arguments_raise():
         lat.set_gas(-1.0, 1.0)
     with pytest.raises(EsbgkError):
         lat.set_wall(0, 1.0, (0.0, 0.1))    # normal wall velocity
+    for gam in (-0.1, 1.5, float("nan")):
+        with pytest.raises(EsbgkError):
+            lat.set_accommodation(0, gam)
+    with pytest.raises(EsbgkError):
+        lat.set_accommodation(2, 0.5)
+    with pytest.raises(EsbgkError):
+        H.gpu_lattice(H.small_cfg("D2Q37", (8, 8), False), "f64").set_accommodation(0, 0.5)
     lat2 = H.gpu_lattice(H.small_cfg("D2Q37", (8, 16), True, Kn=0.5), "f64", scheme="euler")
     with pytest.raises(EsbgkError) as ei:
         lat2.set_gas(0.001, 1.0)            # dt/tau >> 2 with forward Euler
