@@ -39,6 +39,11 @@ integer e_alpha permits exactly):
   0; likewise at the high wall with the plane half a cell above layer
   n - 1. rho_W keeps its definition, so the diffuse part returns the
   fraction gamma of the flux that crossed and the specular part the rest.
+* Unsteady boundary heating (Sec. 4.2): a wall temperature
+  T_W(t) = T + A sin(theta t), t in units of L / sqrt(R T0). The step that
+  advances the stored level n to n + 1 streams during [n dt, (n + 1) dt] and
+  re-emits at the midpoint, T_W((n + 1/2) dt); the moments of level n are
+  those of the pull of that step.
 """
 
 from dataclasses import dataclass, field
@@ -53,6 +58,11 @@ class Wall:
     T: float = 1.0
     u: tuple = (0.0, 0.0, 0.0)
     gamma: float = 1.0      # accommodation: fraction re-emitted diffusely (Sec. 3.2)
+    heat_amp: float = 0.0   # unsteady heating T + heat_amp sin(heat_freq t) (Sec. 4.2)
+    heat_freq: float = 0.0
+
+    def temperature(self, t):
+        return self.T + self.heat_amp * np.sin(self.heat_freq * t)
 
 
 @dataclass
@@ -104,15 +114,27 @@ class Problem:
             lookup = {tuple(v): k for k, v in enumerate(e)}
             self.mirror = np.array([lookup[tuple(v)] for v in flipped])
 
-    def _wall_populations(self, wall):
+    def _wall_populations(self, wall, T=None):
         u = np.asarray(wall.u[: self.D], dtype=np.float64)
         if u[-1] != 0.0:
             raise ValueError("wall velocity must be tangential")
         if not 0.0 <= wall.gamma <= 1.0:
             raise ValueError("accommodation must lie in [0, 1]")
-        E = model.truncated_maxwellian(np.ones(1), u[None, :], np.array([wall.T]),
+        E = model.truncated_maxwellian(np.ones(1), u[None, :], np.array([wall.T if T is None else T]),
                                        self.vs.c, self.vs.w, self.N)
         return E[:, 0]
+
+    def wall_emission(self, n):
+        """S(T_W, u_W) of both walls for the step from level n to n + 1 (wall
+        temperatures at the midpoint (n + 1/2) dt of its streaming)."""
+        t = (n + 0.5) * self.dt
+        out = []
+        for wall, static in ((self.wall_lo, self.E_lo), (self.wall_hi, self.E_hi)):
+            if wall.heat_amp == 0.0:
+                out.append(static)
+            else:
+                out.append(self._wall_populations(wall, wall.temperature(t)))
+        return out
 
     # ---- indexing -------------------------------------------------------
     def flat(self, p):
@@ -169,23 +191,24 @@ def sources(prob, cells):
     return idx, col
 
 
-def wall_density(f, prob, side):
+def wall_density(f, prob, side, E=None):
     """rho_W per wall-parallel column (Sec. 3.2): the populations that cross
     the wall in the coming step, counted once per layer crossed, divided by the
-    matching flux of S(T_W, u_W) re-emitted into the gas."""
+    matching flux of S(T_W, u_W) (E; by default the static wall's) re-emitted
+    into the gas."""
     e_n = prob.vs.e[:, -1]
     nW = prob.dims[-1]
     cols = np.arange(prob.ncols)
     numer = np.zeros(prob.ncols)
     if side == "lo":
-        E = prob.E_lo
+        E = prob.E_lo if E is None else E
         outgoing = np.nonzero(e_n < 0)[0]
         for a in outgoing:
             for k in range(min(-e_n[a], nW)):
                 numer += f[a, cols + k * prob.ncols]
         denom = sum(min(e_n[a], nW) * E[a] for a in np.nonzero(e_n > 0)[0])
     else:
-        E = prob.E_hi
+        E = prob.E_hi if E is None else E
         outgoing = np.nonzero(e_n > 0)[0]
         for a in outgoing:
             for k in range(min(e_n[a], nW)):
@@ -194,10 +217,11 @@ def wall_density(f, prob, side):
     return numer / denom
 
 
-def gather(f, prob, cells=None):
+def gather(f, prob, cells=None, n=0):
     """Streaming: the pre-collision populations fbar_alpha(x) = f_alpha(x -
     e_alpha) of the target cells, with wall ghosts where the source lies beyond
-    a wall. Returns shape (Q, K)."""
+    a wall; f is stored level n (its wall emission is the one of the step from
+    n to n + 1). Returns shape (Q, K)."""
     if cells is None:
         cells = np.arange(prob.M)
     idx, col = sources(prob, cells)
@@ -207,12 +231,13 @@ def gather(f, prob, cells=None):
     inside = idx >= 0
     out[inside] = f[np.broadcast_to(rows, idx.shape)[inside], idx[inside]]
     if prob.walls:
-        rw_lo = wall_density(f, prob, "lo")
-        rw_hi = wall_density(f, prob, "hi")
+        E_lo, E_hi = prob.wall_emission(n)
+        rw_lo = wall_density(f, prob, "lo", E_lo)
+        rw_hi = wall_density(f, prob, "hi", E_hi)
         lo = idx == -1
         hi = idx == -2
-        Elo = np.broadcast_to(prob.E_lo[:, None], idx.shape)
-        Ehi = np.broadcast_to(prob.E_hi[:, None], idx.shape)
+        Elo = np.broadcast_to(E_lo[:, None], idx.shape)
+        Ehi = np.broadcast_to(E_hi[:, None], idx.shape)
         out[lo] = prob.wall_lo.gamma * rw_lo[col[lo]] * Elo[lo]
         out[hi] = prob.wall_hi.gamma * rw_hi[col[hi]] * Ehi[hi]
         # specular part: alpha' = mirror(alpha) from the mirrored layer
@@ -328,20 +353,22 @@ def collide(fbar, prob):
     return fbar - st.omega[None, :] * (fbar - f_es) + st.phi[None, :] * prob.dt * F
 
 
-def step(f, prob):
-    """One time step: stream (with walls) then collide, for every cell."""
-    return collide(gather(f, prob), prob)
+def step(f, prob, n=0):
+    """One time step from stored level n: stream (with walls) then collide,
+    for every cell."""
+    return collide(gather(f, prob, n=n), prob)
 
 
-def step_cells(f, prob, cells):
+def step_cells(f, prob, cells, n=0):
     """One time step evaluated only at the given target cells (for sampled
     comparisons on large grids); returns (Q, K)."""
-    return collide(gather(f, prob, cells), prob)
+    return collide(gather(f, prob, cells, n=n), prob)
 
 
-def run(f, prob, nsteps):
-    for _ in range(nsteps):
-        f = step(f, prob)
+def run(f, prob, nsteps, n0=0):
+    """nsteps steps from stored level n0."""
+    for k in range(nsteps):
+        f = step(f, prob, n0 + k)
     return f
 
 
@@ -353,10 +380,10 @@ def physical_distribution(fbar, prob):
     return f, st
 
 
-def macroscopic(f_state, prob, cells=None):
-    """rho, u, T, sigma, q (eq. mac) of the distribution at the current level:
+def macroscopic(f_state, prob, cells=None, n=0):
+    """rho, u, T, sigma, q (eq. mac) of the distribution at stored level n:
     stream, recover the physical f, take its moments."""
-    fbar = gather(f_state, prob, cells)
+    fbar = gather(f_state, prob, cells, n=n)
     f, _ = physical_distribution(fbar, prob)
     return model.macroscopic(f, prob.vs.c)
 
@@ -380,13 +407,13 @@ def to_deviation(f, prob):
     return f / prob.vs.w[:, None] - 1.0
 
 
-def reductions(f_state, prob, u_prev=None):
+def reductions(f_state, prob, u_prev=None, n=0):
     """Global FP64 sums of the current level: mass sum rho, energy
     sum 1/2 sum_alpha f c^2, momentum sum rho u, the mass flow rate through a
     plane normal to x averaged over the nx planes, dx^(D-1)/nx sum rho u_x,
     and the relative change ||u - u_prev||_2 / ||u||_2 (0 when no previous
     field is given)."""
-    fbar = gather(f_state, prob)
+    fbar = gather(f_state, prob, n=n)
     f, st = physical_distribution(fbar, prob)
     c = prob.vs.c
     mass = st.rho.sum()
