@@ -129,6 +129,17 @@ int esbgk_set_wall(esbgk_ctx* ctx, int side, double T_w, const double u_w[3]);
  * walls or gamma is outside [0, 1]. */
 int esbgk_set_wall_accommodation(esbgk_ctx* ctx, int side, double gamma);
 
+/* Unsteady boundary heating (Sec. 4.2): the temperature of wall `side`
+ * becomes T_W(t) = T_w + amplitude sin(theta t), T_w as set by
+ * esbgk_set_wall, t in units of L / sqrt(R T0) (t = n dt after n steps;
+ * theta is the paper's Strouhal number). The step from stored level n
+ * re-emits at T_W((n + 1/2) dt), the midpoint of its streaming; the wall
+ * tables are rebuilt on the device before every step (also inside the
+ * captured graphs), and read-outs of level n use that step's tables.
+ * amplitude = 0 restores the static wall. E_INVALID if the lattice has no
+ * walls, an argument is not finite or |amplitude| >= T_w. */
+int esbgk_set_wall_heating(esbgk_ctx* ctx, int side, double amplitude, double theta);
+
 /* Body force g[3] (eq. esbgk, its Hermite expansion in Sec. 2.2). */
 int esbgk_set_body_force(esbgk_ctx* ctx, const double g[3]);
 

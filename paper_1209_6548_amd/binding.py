@@ -69,6 +69,7 @@ def lib():
             "esbgk_set_gas": (I, [P, D, D, D]),
             "esbgk_set_wall": (I, [P, I, D, DP]),
             "esbgk_set_wall_accommodation": (I, [P, I, D]),
+            "esbgk_set_wall_heating": (I, [P, I, D, D]),
             "esbgk_set_body_force": (I, [P, DP]),
             "esbgk_init_equilibrium": (I, [P, DP, DP, DP, DP, D]),
             "esbgk_set_populations": (I, [P, DP]),
@@ -210,6 +211,11 @@ class Lattice:
         """Maxwell's wall model: fraction gamma of wall `side` re-emitted
         diffusely, 1 - gamma reflected specularly (default 1)."""
         self._check(lib().esbgk_set_wall_accommodation(self._ctx, int(side), float(gamma)), "set_accommodation")
+
+    def set_heating(self, side, amplitude, theta):
+        """Unsteady heating of wall `side`: T_w + amplitude sin(theta t)."""
+        self._check(lib().esbgk_set_wall_heating(self._ctx, int(side), float(amplitude), float(theta)),
+                    "set_heating")
 
     def set_body_force(self, g):
         gg = np.zeros(3)

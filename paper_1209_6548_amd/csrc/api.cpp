@@ -27,7 +27,7 @@ size_t compute_size(int storage) { return storage == ESBGK_F64 ? 8 : 4; }
 
 // Workspace layout; every region 256-byte aligned.
 struct Layout {
-  size_t pop[2], wp[2], lc, pp, lc64, pp64, uprev, red_part, red_out, staging, total;
+  size_t pop[2], wp[2], lc, pp, lc64, pp64, uprev, red_part, red_out, wprog, level, staging, total;
   size_t staging_bytes;
 };
 
@@ -94,6 +94,8 @@ Layout layout_of(const esbgk_shape* s) {
   L.uprev = take(D * cells * cs);
   L.red_part = take(nblocks * NRED * sizeof(double));
   L.red_out = take(NRED * sizeof(double));
+  L.wprog = take(sizeof(WallProgram));
+  L.level = take(sizeof(int64_t));
   const size_t stage_cells = std::min<size_t>(cells, STAGE_CELLS);
   const size_t per_cell = std::max<size_t>(nfields(int(D)), 2 + D + Q) * sizeof(double);
   L.staging_bytes = stage_cells * per_cell;
@@ -124,6 +126,9 @@ struct esbgk_ctx {
   double Tw[2] = {1.0, 1.0};
   double uw[2][3] = {{0, 0, 0}, {0, 0, 0}};
   double gam[2] = {1.0, 1.0};     // wall accommodation (Maxwell's model)
+  double heat_amp[2] = {0, 0}, heat_freq[2] = {0, 0};   // unsteady heating
+  bool heating() const { return heat_amp[0] != 0.0 || heat_amp[1] != 0.0; }
+  WallProgram wprog{};
   double g[3] = {0, 0, 0};
   int n_ref = 0;
   // host copies of the device parameter blocks
@@ -186,6 +191,23 @@ StepArgs args_at(const esbgk_ctx* c, int cur) {
 
 StepArgs base_args(const esbgk_ctx* c) { return args_at(c, c->cur); }
 
+// Unsteady heating: rebuild the wall tables for the step from the level held
+// on the device (advance: and move that level on, as a step does).
+hipError_t wall_tables(const esbgk_ctx* c, int advance, hipStream_t stream) {
+  return launch_wall_tables(c->shape.velset, reinterpret_cast<const WallProgram*>(c->at(c->lay.wprog)),
+                            c->at(c->lay.lc64), c->at(c->lay.pp64), c->f64() ? nullptr : c->at(c->lay.pp),
+                            reinterpret_cast<int64_t*>(c->at(c->lay.level)), advance, stream);
+}
+
+// Copy the host step counter to the device level (after the state was set).
+int sync_level(esbgk_ctx* c) {
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->at(c->lay.level), &c->steps, sizeof(int64_t), hipMemcpyHostToDevice, c->stream),
+              "level");
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "level");
+  return ESBGK_OK;
+}
+
+
 void drop_graphs(esbgk_ctx* c) {
   for (int p = 0; p < 2; ++p) {
     if (c->graph[p]) (void)hipGraphExecDestroy(c->graph[p]);
@@ -208,7 +230,8 @@ int build_graph(esbgk_ctx* c, int parity) {
   for (int i = 0; i < c->graph_steps && le == hipSuccess; ++i) {
     StepArgs a = args_at(c, cur);
     a.stream = c->cap;
-    le = launch_step(c->shape.velset, c->shape.storage, a);
+    if (c->heating()) le = wall_tables(c, 1, c->cap);
+    if (le == hipSuccess) le = launch_step(c->shape.velset, c->shape.storage, a);
     cur ^= 1;
   }
   hipGraph_t g = nullptr;
@@ -232,6 +255,15 @@ int upload_params(esbgk_ctx* c) {
       make_problem(*c->lat, c->n_ref, c->shape.scheme, c->Kn, c->Pr, c->varpi, c->g, c->Tw, c->uw, c->gam);
   pack_params<double>(hp, c->lat->Q, c->pp64);
   HIP_OR_FAIL(c, hipMemcpyAsync(c->at(c->lay.pp64), &c->pp64, sizeof(c->pp64), hipMemcpyHostToDevice, c->stream),
+              "upload parameters");
+  for (int side = 0; side < 2; ++side) {
+    c->wprog.T[side] = c->Tw[side];
+    c->wprog.amp[side] = c->heat_amp[side];
+    c->wprog.freq[side] = c->heat_freq[side];
+    for (int i = 0; i < 3; ++i) c->wprog.u[side][i] = c->uw[side][i];
+  }
+  c->wprog.dt = hp.dt;
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->at(c->lay.wprog), &c->wprog, sizeof(c->wprog), hipMemcpyHostToDevice, c->stream),
               "upload parameters");
   if (!c->f64()) {
     pack_params<float>(hp, c->lat->Q, c->pp32);
@@ -398,6 +430,8 @@ int esbgk_set_wall(esbgk_ctx* c, int side, double T_w, const double u_w[3]) {
   if (u_w[W] != 0.0) return set_err(c, ESBGK_E_INVALID, "wall velocity must be tangential");
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(u_w[i])) return set_err(c, ESBGK_E_INVALID, "u_w must be finite");
+  if (!(T_w - std::fabs(c->heat_amp[side]) > 0.0))
+    return set_err(c, ESBGK_E_INVALID, "the wall temperature must stay > 0 under the heating amplitude");
   c->Tw[side] = T_w;
   for (int i = 0; i < 3; ++i) c->uw[side][i] = i < c->lat->D ? u_w[i] : 0.0;
   return upload_params(c);
@@ -410,6 +444,23 @@ int esbgk_set_wall_accommodation(esbgk_ctx* c, int side, double gamma) {
   if (!(gamma >= 0.0 && gamma <= 1.0)) return set_err(c, ESBGK_E_INVALID, "gamma must lie in [0, 1]");
   c->gam[side] = gamma;
   return upload_params(c);
+}
+
+int esbgk_set_wall_heating(esbgk_ctx* c, int side, double amplitude, double theta) {
+  CHECK_CTX(c);
+  if (!c->shape.walls) return set_err(c, ESBGK_E_INVALID, "lattice has no walls");
+  if (side != 0 && side != 1) return set_err(c, ESBGK_E_INVALID, "side must be 0 or 1");
+  if (!std::isfinite(amplitude) || !std::isfinite(theta))
+    return set_err(c, ESBGK_E_INVALID, "amplitude and theta must be finite");
+  if (!(c->Tw[side] - std::fabs(amplitude) > 0.0))
+    return set_err(c, ESBGK_E_INVALID, "the wall temperature must stay > 0 (|amplitude| < T_w)");
+  const bool was = c->heating();
+  c->heat_amp[side] = amplitude;
+  c->heat_freq[side] = theta;
+  if (c->heating() != was) drop_graphs(c);   // captured graphs carry the table rebuilds or not
+  int rc = upload_params(c);
+  if (rc) return rc;
+  return sync_level(c);
 }
 
 int esbgk_set_body_force(esbgk_ctx* c, const double g[3]) {
@@ -466,7 +517,7 @@ int esbgk_init_equilibrium(esbgk_ctx* c, const double* rho, const double* u, con
   c->steps = 0;
   c->have_prev = 0;
   c->last_red_step = -1;
-  return ESBGK_OK;
+  return sync_level(c);
 }
 
 }  // extern "C"
@@ -530,7 +581,7 @@ int esbgk_set_populations(esbgk_ctx* c, const double* h) {
   c->steps = 0;
   c->have_prev = 0;
   c->last_red_step = -1;
-  return ESBGK_OK;
+  return sync_level(c);
 }
 
 int esbgk_get_populations(esbgk_ctx* c, double* h) {
@@ -584,7 +635,7 @@ int esbgk_set_state(esbgk_ctx* c, const void* h_raw, size_t nbytes) {
   std::memcpy(&c->steps, static_cast<const char*>(h_raw) + pop, sizeof(int64_t));
   c->state_set = true;
   c->have_prev = 0;
-  return ESBGK_OK;
+  return sync_level(c);
 }
 
 int esbgk_step(esbgk_ctx* c, int64_t n) {
@@ -618,6 +669,7 @@ int esbgk_step(esbgk_ctx* c, int64_t n) {
     StepArgs a = base_args(c);
     const bool red = c->R > 0 && ((c->steps + 1) % c->R == 0);
     a.reduce = red ? 1 : 0;
+    if (c->heating()) HIP_OR_FAIL(c, wall_tables(c, 1, c->stream), "wall tables");
     HIP_OR_FAIL(c, launch_step(c->shape.velset, c->shape.storage, a), "step");
     if (red) {
       HIP_OR_FAIL(c, launch_reduce_finalize(a.red_part, nblocks, reinterpret_cast<double*>(c->at(c->lay.red_out)),
@@ -642,6 +694,7 @@ int esbgk_read_moments(esbgk_ctx* c, double* h_out, int* F) {
   double* st = reinterpret_cast<double*>(c->at(c->lay.staging));
   std::vector<double> tmp;
   StepArgs a = base_args(c);
+  if (c->heating()) HIP_OR_FAIL(c, wall_tables(c, 0, c->stream), "wall tables");
   for (uint32_t c0 = 0; c0 < cells; c0 += STAGE_CELLS) {
     const uint32_t n = std::min(STAGE_CELLS, cells - c0);
     HIP_OR_FAIL(c, launch_moments(c->shape.velset, c->shape.storage, a, c0, n, st), "moments");
@@ -659,6 +712,7 @@ int esbgk_reduce(esbgk_ctx* c, double out[8]) {
   if (!c->state_set) return set_err(c, ESBGK_E_STATE, "no state set");
   const uint32_t nblocks = slot_blocks(c->geo);
   StepArgs a = base_args(c);
+  if (c->heating()) HIP_OR_FAIL(c, wall_tables(c, 0, c->stream), "wall tables");
   HIP_OR_FAIL(c, launch_reduce(c->shape.velset, c->shape.storage, a), "reduce");
   HIP_OR_FAIL(c, launch_reduce_finalize(a.red_part, nblocks, reinterpret_cast<double*>(c->at(c->lay.red_out)),
                                         c->stream), "reduce");

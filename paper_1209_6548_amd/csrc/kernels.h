@@ -37,5 +37,9 @@ hipError_t launch_moments(int velset, int storage, const StepArgs& a, uint32_t c
 hipError_t launch_init(int velset, int storage, const StepArgs& a, double r, const double* rho, const double* u,
                        const double* T, const double* noise, double amp, uint32_t c0, uint32_t count);
 hipError_t launch_wall_partials(int velset, int storage, const StepArgs& a);
+// Rebuild the wall tables of pp64 (and of pp32 when not null) for the step
+// from the level held in *level; advance: then increment *level.
+hipError_t launch_wall_tables(int velset, const WallProgram* prog, const void* lc64, void* pp64, void* pp32,
+                              int64_t* level, int advance, hipStream_t stream);
 
 }  // namespace esbgk

@@ -249,6 +249,56 @@ __device__ __forceinline__ double shat_m1(int a, double r, const double* u, doub
   return s;
 }
 
+// Wall tables for the step from stored level *level (unsteady heating): one
+// workgroup, thread a evaluates S(T_W, u_W)/w - 1 at velocity a for both
+// walls, thread 0 sums the flux terms in velocity order and, if advance,
+// moves the level on.
+template <class L>
+__global__ void __launch_bounds__(64)
+k_wall_tables(const WallProgram* __restrict__ prog, const LatConsts<double>* __restrict__ lc,
+              ProbParams<double>* __restrict__ pp64, ProbParams<float>* __restrict__ pp32,
+              int64_t* __restrict__ level, int advance) {
+  constexpr int Q = L::Q, W = L::D - 1;
+  __shared__ double em1[2][Q];
+  const int a = int(threadIdx.x);
+  const double t = (double(*level) + 0.5) * prog->dt;
+  if (a < Q) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const double th = prog->T[side] + prog->amp[side] * sin(prog->freq[side] * t) - 1.0;
+      const double v = shat_m1<L>(a, lc->r, prog->u[side], th);
+      em1[side][a] = v;
+      pp64->Em1[side][a] = v;
+      pp64->Ehat[side][a] = 1.0 + v;
+      if (pp32) {
+        pp32->Em1[side][a] = float(v);
+        pp32->Ehat[side][a] = float(1.0 + v);
+      }
+    }
+  }
+  __syncthreads();
+  if (a == 0) {
+    for (int side = 0; side < 2; ++side) {
+      double leave = 0.0, den = 0.0;
+      for (int b = 0; b < Q; ++b) {
+        const int en = ecomp<L>(b, W);
+        const bool out = side == 0 ? en < 0 : en > 0;
+        const bool in = side == 0 ? en > 0 : en < 0;
+        const double k = double(en < 0 ? -en : en);
+        if (out) leave += k * lc->w[b];
+        if (in) den += k * lc->w[b] * (1.0 + em1[side][b]);
+      }
+      pp64->K0[side] = leave / den - 1.0;
+      pp64->invden[side] = 1.0 / den;
+      if (pp32) {
+        pp32->K0[side] = float(leave / den - 1.0);
+        pp32->invden[side] = float(1.0 / den);
+      }
+    }
+    if (advance) *level += 1;
+  }
+}
+
 // Equilibrium initial state h = rho Shat (1 + amp xi) - 1 for cells
 // [c0, c0 + count); fields are [count] / [D][count] / [Q][count] or null.
 template <class L, typename S>
@@ -399,6 +449,22 @@ hipError_t launch_init(int velset, int storage, const StepArgs& a, double r, con
 
 hipError_t launch_wall_partials(int velset, int storage, const StepArgs& a) {
   ESBGK_DISPATCH(velset, storage, (partials_t<L, S>(a)));
+}
+
+template <class L>
+static hipError_t wall_tables_t(const WallProgram* prog, const void* lc64, void* pp64, void* pp32, int64_t* level,
+                                int advance, hipStream_t stream) {
+  hipLaunchKernelGGL(k_wall_tables<L>, dim3(1), dim3(64), 0, stream, prog,
+                     static_cast<const LatConsts<double>*>(lc64), static_cast<ProbParams<double>*>(pp64),
+                     static_cast<ProbParams<float>*>(pp32), level, advance);
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_tables(int velset, const WallProgram* prog, const void* lc64, void* pp64, void* pp32,
+                              int64_t* level, int advance, hipStream_t stream) {
+  if (velset == 1) return wall_tables_t<D2Q37>(prog, lc64, pp64, pp32, level, advance, stream);
+  if (velset == 2) return wall_tables_t<D3Q39>(prog, lc64, pp64, pp32, level, advance, stream);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace esbgk

@@ -52,6 +52,16 @@ struct ProbParams {
   int specular;
 };
 
+// Unsteady boundary heating (Sec. 4.2): wall temperatures
+// T_W(t) = T[side] + amp[side] sin(freq[side] t). Before a step from stored
+// level n the device rebuilds the wall tables of ProbParams (Em1, Ehat, K0,
+// invden) at t = (n + 1/2) dt, the midpoint of that step's streaming.
+struct WallProgram {
+  double T[2], amp[2], freq[2];
+  double u[2][3];
+  double dt;
+};
+
 // Division by a run-time constant d for n < 2^31: q = (umulhi(n, m) + n) >> l
 // with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1.
 struct FastDiv {

@@ -37,8 +37,9 @@ def oracle_problem(cfg, scheme="trapezoid"):
               g=tuple(cfg.get("g", (0, 0, 0))), scheme=scheme, n_ref=cfg.get("n_ref", 0))
     if kw["walls"]:
         gam = cfg.get("gamma", (1.0, 1.0))
-        kw["wall_lo"] = OL.Wall(cfg["T_w"][0], tuple(cfg["u_w"][0]), gam[0])
-        kw["wall_hi"] = OL.Wall(cfg["T_w"][1], tuple(cfg["u_w"][1]), gam[1])
+        heat = cfg.get("heating", ((0.0, 0.0), (0.0, 0.0)))
+        kw["wall_lo"] = OL.Wall(cfg["T_w"][0], tuple(cfg["u_w"][0]), gam[0], *heat[0])
+        kw["wall_hi"] = OL.Wall(cfg["T_w"][1], tuple(cfg["u_w"][1]), gam[1], *heat[1])
     return OL.Problem(vs, tuple(cfg["dims"]), **kw)
 
 
@@ -54,13 +55,16 @@ def gpu_lattice(cfg, storage=None, scheme="trapezoid"):
         if "gamma" in cfg:
             lat.set_accommodation(0, cfg["gamma"][0])
             lat.set_accommodation(1, cfg["gamma"][1])
+        if "heating" in cfg:
+            lat.set_heating(0, *cfg["heating"][0])
+            lat.set_heating(1, *cfg["heating"][1])
     lat.set_body_force(cfg.get("g", (0, 0, 0)))
     return lat
 
 
-def oracle_fields(f, prob, cells=None):
-    """The oracle's eq. mac fields in the library's layout."""
-    rho, u, T, sigma, q = OL.macroscopic(f, prob, cells)
+def oracle_fields(f, prob, cells=None, n=0):
+    """The oracle's eq. mac fields of stored level n in the library's layout."""
+    rho, u, T, sigma, q = OL.macroscopic(f, prob, cells, n=n)
     D = prob.D
     sig = np.array([sigma[:, i, j] for i in range(D) for j in range(i, D)])
     return {"rho": rho, "u": u.T.copy(), "T": T, "sigma": sig, "q": q.T.copy()}
