@@ -128,6 +128,27 @@ def bench_batch(r, steps, warmup, fp64_sample=16):
     return out
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Context for the roofline: read+write GB/s of a plain device-to-device
+    copy of nbytes (torch's copy, timed with HIP events)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def measured_traffic(storage):
     """HBM bytes per step launch on the headline workload from the FETCH_SIZE /
     WRITE_SIZE counters (calibrated against a copy of known size), or None if
@@ -256,6 +277,10 @@ def main():
         key = f"{ch['name']}_f16"
         variants[key] = bench_single(ch, "f16", max(10, args.steps // 10), 3)
         log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
+    copy_gbs = None
+    if not args.only_main:
+        copy_gbs = copy_bandwidth()
+        log(f"device copy: {copy_gbs:.0f} GB/s")
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")
@@ -276,7 +301,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_over_algorithmic": (round(traffic / (main_run["bytes_per_cell"] * 1024 * 1024), 4)
                                                   if traffic else None),
-                     "kernel": f"k_step<D2Q37, {args.storage}>", "bytes_per_cell": main_run["bytes_per_cell"]},
+                     "kernel": f"k_step<D2Q37, {args.storage}>", "bytes_per_cell": main_run["bytes_per_cell"],
+                     "device_copy_GBs": round(copy_gbs, 1) if copy_gbs else None},
         "cpu_baseline": cpu,
         "variants": variants,
     }
