@@ -23,6 +23,9 @@ The oracle is written in plain numpy, in float64, directly from the paper:
   diffuse (Maxwell, gamma = 1) wall of Sec. 3.2, collision and force with a
   forward-Euler or trapezoidal time discretisation of eq. lbgk, macroscopic
   output and FP64 reductions.
+* ``offlattice`` - the paper's own scheme (Sec. 3.1) on its own velocity set:
+  the 6-point Gauss-Hermite product set, forward Euler in time and TVD minmod
+  finite-volume fluxes in space, periodic boundaries.
 
 Where the paper is silent or ambiguous, the reading taken is stated in the
 docstring of the function that depends on it.
@@ -30,7 +33,7 @@ docstring of the function that depends on it.
 
 import importlib as _il
 
-for _m in ("quadrature", "hermite", "model", "lattice"):
+for _m in ("quadrature", "hermite", "model", "lattice", "offlattice"):
     try:
         _il.import_module(f"{__name__}.{_m}")
     except ModuleNotFoundError:
