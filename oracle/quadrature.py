@@ -36,12 +36,31 @@ def hermite_rule_1d(n):
     """1-D Gauss-Hermite rule of Sec. 2.2: abscissae are the n roots of the
     probabilists' Hermite polynomial He_n, weights from eq. weight,
     w_alpha = n! / [n He_{n-1}(c_alpha)]^2 (normalised to the weight function
-    exp(-c^2/2)/sqrt(2 pi), so the weights sum to one)."""
-    roots = He.hermeroots([0] * n + [1])           # library root finder
-    he_nm1 = He.hermeval(roots, [0] * (n - 1) + [1])
-    w = factorial(n) / (n * he_nm1) ** 2
-    order = np.argsort(roots)
-    return roots[order], w[order]
+    exp(-c^2/2)/sqrt(2 pi), so the weights sum to one).
+
+    The library root finder's roots are refined by Newton's method on He_n in
+    50-digit arithmetic and both formulas are evaluated there, so abscissae
+    and weights are the correctly rounded doubles (in plain double precision
+    the outer weight of n = 6 would carry a relative error near 2e-14)."""
+
+    def he(k, x):                                   # He_{k+1} = x He_k - k He_{k-1}
+        p0, p1 = mp.mpf(1), x
+        if k == 0:
+            return p0
+        for j in range(1, k):
+            p0, p1 = p1, x * p1 - j * p0
+        return p1
+
+    start = np.sort(He.hermeroots([0] * n + [1]))
+    roots, w = np.empty(n), np.empty(n)
+    with mp.workdps(50):
+        for i, x0 in enumerate(start):
+            x = mp.mpf(float(x0))
+            for _ in range(8):                      # He_n' = n He_{n-1}
+                x = x - he(n, x) / (n * he(n - 1, x))
+            roots[i] = float(x)
+            w[i] = float(mp.factorial(n) / (n * he(n - 1, x)) ** 2)
+    return roots, w
 
 
 def _orbit(v):
