@@ -59,7 +59,8 @@ enum {
   ESBGK_E_STATE = -6      /* call out of order (e.g. step before the state is set) */
 };
 
-enum { ESBGK_D2Q37 = 1, ESBGK_D3Q39 = 2 };            /* velocity set */
+enum { ESBGK_D2Q37 = 1, ESBGK_D3Q39 = 2,             /* on-lattice velocity sets */
+       ESBGK_D2Q36GH = 3 };                          /* 6-point Gauss-Hermite product set (esbgk_tvd_*) */
 enum { ESBGK_F64 = 0, ESBGK_F32 = 1, ESBGK_F16 = 2 };  /* storage of h; FP64 computes in FP64, the others in FP32 */
 enum { ESBGK_TRAPEZOID = 0, ESBGK_EULER = 1 };         /* time discretisation of eq. lbgk */
 
@@ -245,6 +246,63 @@ int esbgk_batch_layout(const esbgk_batch* b, int* threads, int* nbins);
 int esbgk_batch_autotune(esbgk_batch* b, int steps_per_trial);
 int64_t esbgk_batch_steps_done(const esbgk_batch* b);
 const char* esbgk_batch_last_error(const esbgk_batch* b);
+
+/* ---- The paper's own scheme (Sec. 3.1) ----------------------------------
+ * The velocity set of the paper: the tensor product of the 6-point
+ * Gauss-Hermite rule of eq. weight (ESBGK_D2Q36GH: 36 velocities, exact to
+ * degree 11 along each axis, carrying the N = 4 expansion). Its abscissae lie
+ * off the lattice, so streaming is the paper's finite-difference update:
+ * forward Euler in time and, along each axis, the second-order TVD flux
+ * difference with the minmod limiter,
+ *   f^{n+1} = f^n - nu_x [F_{i+1/2} - F_{i-1/2}] - nu_y [F_{j+1/2} - F_{j-1/2}]
+ *             + (dt/tau)(f^ES - f^n) + dt F,   nu = c dt / dx,
+ * with F_{i+1/2} = f_i + (1 - nu)/2 (f_{i+1} - f_i) Psi(Theta_i) for c > 0 and
+ * its mirror image (upwind cell i + 1) for c < 0. Every term is evaluated at
+ * level n; one fused kernel launch per step. The stored state is the
+ * physical f (deviational h = f/w - 1 in the storage type, in the velocity
+ * order of esbgk_tvd_info). Boundaries: periodic in x and y.
+ *
+ * Shape: velset = ESBGK_D2Q36GH, nz = 1, walls = 0, scheme = ESBGK_EULER,
+ * storage F64 / F32 / F16 (FP32 compute for the last two), n_ref = N_L
+ * (0: nx). The time step is dt = cfl dx / max|c| with dx = 1/N_L and
+ * 0 < cfl <= 1. */
+typedef struct esbgk_tvd esbgk_tvd;
+
+/* Abscissae c[36][2] and weights w[36] of ESBGK_D2Q36GH (either may be
+ * NULL), derived on the host from the roots of He_6 and eq. weight. */
+int esbgk_tvd_info(double* c, double* w);
+/* Device workspace bytes for the shape (0 if invalid). */
+size_t esbgk_tvd_workspace_bytes(const esbgk_shape* shape);
+/* New handle on a caller-allocated, 256-byte-aligned workspace and a HIP
+ * stream. Gas defaults: Kn = 0.1, Pr = 1, varpi = 0.5; g = 0. Errors:
+ * E_INVALID (shape, cfl), E_NOMEM (workspace), E_HIP; the reason is in
+ * esbgk_tvd_last_error(NULL). */
+int esbgk_tvd_create(const esbgk_shape* shape, double cfl, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                     esbgk_tvd** out);
+int esbgk_tvd_destroy(esbgk_tvd* t);
+/* dt of the handle (nondimensional). */
+double esbgk_tvd_time_step(const esbgk_tvd* t);
+/* Gas (as esbgk_set_gas); E_UNSTABLE when forward Euler is unstable at
+ * rho = T = 1 (dt/tau >= 2 or dt/(Pr tau) >= 2). */
+int esbgk_tvd_set_gas(esbgk_tvd* t, double Kn, double Pr, double varpi);
+int esbgk_tvd_set_body_force(esbgk_tvd* t, const double g[3]);
+/* Initial state f = rho S(T, u) (1 + amplitude noise) as
+ * esbgk_init_equilibrium (u is [2][cells], noise [36][cells]). */
+int esbgk_tvd_init_equilibrium(esbgk_tvd* t, const double* rho, const double* u, const double* T,
+                               const double* noise, double amplitude);
+/* Stored populations as FP64 h[36][cells] (host); set rounds to the storage
+ * type and resets the step counter. */
+int esbgk_tvd_set_populations(esbgk_tvd* t, const double* h);
+int esbgk_tvd_get_populations(esbgk_tvd* t, double* h);
+/* Advance n steps (asynchronous on the handle's stream). */
+int esbgk_tvd_step(esbgk_tvd* t, int64_t n);
+/* rho, u[2], T, sigma (xx, xy, yy), q[2] of the stored f per cell, as
+ * [9][cells] FP64 (FP64 arithmetic); synchronises. */
+int esbgk_tvd_read_moments(esbgk_tvd* t, double* h_out, int* F);
+int64_t esbgk_tvd_steps_done(const esbgk_tvd* t);
+/* Text of the last error on the handle; with NULL, why the last create on
+ * this thread failed. */
+const char* esbgk_tvd_last_error(const esbgk_tvd* t);
 
 #ifdef __cplusplus
 }

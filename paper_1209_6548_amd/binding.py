@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libesbgk.so")
 
 OK, E_INVALID, E_NOMEM, E_HIP, E_NONFINITE, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5, -6
-D2Q37, D3Q39 = 1, 2
+D2Q37, D3Q39, D2Q36GH = 1, 2, 3
 F64, F32, F16 = 0, 1, 2
 TRAPEZOID, EULER = 0, 1
 
@@ -97,6 +97,20 @@ def lib():
             "esbgk_batch_autotune": (I, [P, I]),
             "esbgk_batch_steps_done": (I64, [P]),
             "esbgk_batch_last_error": (ctypes.c_char_p, [P]),
+            "esbgk_tvd_info": (I, [DP, DP]),
+            "esbgk_tvd_workspace_bytes": (SZ, [P]),
+            "esbgk_tvd_create": (I, [P, D, P, SZ, P, P]),
+            "esbgk_tvd_destroy": (I, [P]),
+            "esbgk_tvd_time_step": (D, [P]),
+            "esbgk_tvd_set_gas": (I, [P, D, D, D]),
+            "esbgk_tvd_set_body_force": (I, [P, DP]),
+            "esbgk_tvd_init_equilibrium": (I, [P, DP, DP, DP, DP, D]),
+            "esbgk_tvd_set_populations": (I, [P, DP]),
+            "esbgk_tvd_get_populations": (I, [P, DP]),
+            "esbgk_tvd_step": (I, [P, I64]),
+            "esbgk_tvd_read_moments": (I, [P, DP, P]),
+            "esbgk_tvd_steps_done": (I64, [P]),
+            "esbgk_tvd_last_error": (ctypes.c_char_p, [P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -373,3 +387,99 @@ class Batch:
         h = np.empty((self.Q, self.cells[i]))
         self._check(lib().esbgk_batch_get_populations(self._b, int(i), _dp(h)), "batch_populations")
         return h
+
+
+def tvd_velocity_set():
+    """Abscissae c[36][2] and weights w[36] of the 6-point Gauss-Hermite
+    product set of the paper's own scheme."""
+    c = np.empty((36, 2))
+    w = np.empty(36)
+    rc = lib().esbgk_tvd_info(_dp(c), _dp(w))
+    if rc:
+        raise EsbgkError(rc, "tvd_info")
+    return c, w
+
+
+class TVDLattice:
+    """The paper's own scheme (forward Euler, TVD minmod fluxes) on the
+    6-point Gauss-Hermite product set D2Q36, periodic in x and y."""
+
+    Q, D, N = 36, 2, 4
+
+    def __init__(self, nx=64, ny=64, storage="f32", cfl=0.5, n_ref=0, device="cuda:0"):
+        import torch
+        self.device = torch.device(device)
+        self.dims = (nx, ny)
+        self.cells = nx * ny
+        self.storage = storage
+        self.shape = Shape(D2Q36GH, nx, ny, 1, 0, _STORAGE[storage], EULER, n_ref)
+        L = lib()
+        nbytes = L.esbgk_tvd_workspace_bytes(ctypes.byref(self.shape))
+        if nbytes == 0:
+            raise EsbgkError(E_INVALID, "invalid shape")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._t = ctypes.c_void_p()
+        rc = L.esbgk_tvd_create(ctypes.byref(self.shape), float(cfl), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                _stream_ptr(self.device), ctypes.byref(self._t))
+        if rc:
+            msg = L.esbgk_tvd_last_error(None)
+            raise EsbgkError(rc, f"tvd_create: {msg.decode() if msg else ''}")
+        self.c, self.w = tvd_velocity_set()
+
+    def _check(self, rc, what):
+        if rc:
+            msg = lib().esbgk_tvd_last_error(self._t)
+            raise EsbgkError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "_t", None) and self._t.value:
+            lib().esbgk_tvd_destroy(self._t)
+            self._t = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def dt(self):
+        return lib().esbgk_tvd_time_step(self._t)
+
+    @property
+    def steps_done(self):
+        return lib().esbgk_tvd_steps_done(self._t)
+
+    def set_gas(self, Kn, Pr, varpi=0.5):
+        self._check(lib().esbgk_tvd_set_gas(self._t, Kn, Pr, varpi), "tvd_set_gas")
+
+    def set_body_force(self, g):
+        gg = np.zeros(3)
+        gg[:len(g)] = g
+        self._check(lib().esbgk_tvd_set_body_force(self._t, _dp(gg)), "tvd_set_body_force")
+
+    def init_equilibrium(self, rho=None, u=None, T=None, noise=None, amplitude=0.0):
+        rho = _f64(rho, (self.cells,))
+        u = _f64(u, (self.D, self.cells))
+        T = _f64(T, (self.cells,))
+        noise = _f64(noise, (self.Q, self.cells))
+        self._check(lib().esbgk_tvd_init_equilibrium(self._t, _dp(rho), _dp(u), _dp(T), _dp(noise),
+                                                     float(amplitude)), "tvd_init_equilibrium")
+
+    def set_populations(self, h):
+        h = _f64(h, (self.Q, self.cells))
+        self._check(lib().esbgk_tvd_set_populations(self._t, _dp(h)), "tvd_set_populations")
+
+    def get_populations(self):
+        h = np.empty((self.Q, self.cells))
+        self._check(lib().esbgk_tvd_get_populations(self._t, _dp(h)), "tvd_get_populations")
+        return h
+
+    def step(self, n=1):
+        self._check(lib().esbgk_tvd_step(self._t, int(n)), "tvd_step")
+
+    def read_moments(self):
+        out = np.empty((9, self.cells))
+        f = ctypes.c_int()
+        self._check(lib().esbgk_tvd_read_moments(self._t, _dp(out), ctypes.byref(f)), "tvd_read_moments")
+        return split_fields(out, self.D)

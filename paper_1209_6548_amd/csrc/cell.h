@@ -261,14 +261,18 @@ __device__ __forceinline__ void physical_a3(const RawMoments<L, C>& m, const Cel
 
 // ---- collision -----------------------------------------------------------
 
+// Polynomial coefficients of the post-collision update: with
+// c^(n) = omega a_ES^(n) + phi dt a_F^(n) (Sec. 2.2), the relaxation adds
+//   w_alpha sum_n c^(n) : chi^(n)(c_alpha) / n!
+// which, expanded in powers of e = c / r, is K0 + K1.e + K2:ee + K3:eee +
+// K4:eeee (for the deviational h, c^(0) - omega is omega (rho - 1)).
 template <class L, typename C>
-__device__ __forceinline__ void collide(C (&h)[L::Q], const LatConsts<C>* __restrict__ lc,
-                                        const ProbParams<C>* __restrict__ pp, CellState<L, C>& s) {
-  constexpr int D = L::D, P = L::P, N = L::N;
+__device__ __forceinline__ void poly_coeffs(const RawMoments<L, C>& m, const CellState<L, C>& s,
+                                            const LatConsts<C>* __restrict__ lc,
+                                            const ProbParams<C>* __restrict__ pp, C& K0, C (&K1)[3], C (&K2)[3][3],
+                                            C (&K3)[3][3][3], C (&K4)[3][3][3][3]) {
+  constexpr int D = L::D, N = L::N;
   const bool force = pp->force != 0;
-  RawMoments<L, C> m;
-  raw_moments<L, C>(h, lc, N >= 4 && force, m);
-  reconstruct<L, C>(m, lc, pp, s);
 
   const C om = s.omega;
   const C cf = s.phi * pp->dt;   // weight of the force coefficients
@@ -336,8 +340,7 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const LatConsts<C>* __rest
 
   // polynomial coefficients in e (c = r e)
   const C r = lc->r, r2 = r * r, r3 = r2 * r, r4 = r2 * r2;
-  C K0 = om * s.drho;
-  C K1[3], K2[3][3], K3[3][3][3];
+  K0 = om * s.drho;
   {
     C tr2 = C(0);
 #pragma unroll
@@ -379,7 +382,6 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const LatConsts<C>* __rest
 #pragma unroll
       for (int k = 0; k < D; ++k) K3[i][j][k] = r3 * C(1.0 / 6.0) * c3[i][j][k];
 
-  C K4[3][3][3][3];
   if constexpr (N >= 4) {
 #pragma unroll
     for (int i = 0; i < D; ++i)
@@ -391,6 +393,19 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const LatConsts<C>* __rest
           for (int l = k; l < D; ++l) K4[i][j][k][l] = r4 * C(1.0 / 24.0) * c4[i][j][k][l];
   }
 
+}
+
+template <class L, typename C>
+__device__ __forceinline__ void collide(C (&h)[L::Q], const LatConsts<C>* __restrict__ lc,
+                                        const ProbParams<C>* __restrict__ pp, CellState<L, C>& s) {
+  constexpr int D = L::D, P = L::P, N = L::N;
+  const bool force = pp->force != 0;
+  RawMoments<L, C> m;
+  raw_moments<L, C>(h, lc, N >= 4 && force, m);
+  reconstruct<L, C>(m, lc, pp, s);
+  C K0, K1[3], K2[3][3], K3[3][3][3], K4[3][3][3][3];
+  poly_coeffs<L, C>(m, s, lc, pp, K0, K1, K2, K3, K4);
+  const C om = s.omega;
   const C omw = C(1) - om;
   h[0] = fmac(omw, h[0], K0);
 #pragma unroll

@@ -1,0 +1,198 @@
+// The paper's own velocity set and scheme (Sec. 2.2, Sec. 3.1): the tensor
+// product of the 6-point Gauss-Hermite rule of eq. weight (exact to degree
+// 11 along each axis, carrying the N = 4 expansion), with forward Euler in
+// time and TVD minmod finite-volume fluxes in space.
+//
+// The abscissae are off the lattice. Velocity alpha of the 2-D set is
+// (xi_{kx}, xi_{ky}) with signed root ranks k: xi_{+-1} = +-0.617...,
+// xi_{+-2} = +-1.889..., xi_{+-3} = +-3.324.... The root values and weights
+// are derived on the host at start-up; here only the ranks are compile-time.
+//
+// Velocity order (shared with the population I/O): the 18 representatives
+// (first component positive) sorted by |c|^2 and then by descending rank
+// tuple, followed by their opposites at alpha + 18.
+#pragma once
+
+#include "cell.h"
+
+namespace esbgk {
+
+struct D2Q36GH {
+  static constexpr int D = 2;
+  static constexpr int Q = 36;
+  static constexpr int P = 18;
+  static constexpr int N = 4;
+  static constexpr int K[P][2] = {
+      {1, 1},  {1, -1},  {2, 1},  {2, -1},  {1, 2},  {1, -2},  {2, 2},  {2, -2},  {3, 1},
+      {3, -1}, {1, 3},   {1, -3}, {3, 2},   {3, -2}, {2, 3},   {2, -3}, {3, 3},   {3, -3},
+  };
+};
+
+// Sign of component i of velocity alpha (alpha < 36).
+__host__ __device__ constexpr int gh_sign(int alpha, int i) {
+  return (alpha < D2Q36GH::P ? 1 : -1) * (D2Q36GH::K[alpha % D2Q36GH::P][i] > 0 ? 1 : -1);
+}
+
+// Number of monomials c^n, n = 1..4, of a 2-D velocity: x y | xx xy yy |
+// xxx xxy xyy yyy | xxxx xxxy xxyy xyyy yyyy.
+constexpr int GH_MONO = 14;
+
+// Per-set constants of the scheme (device memory, built on the host):
+//   w     weight of representative p (its opposite has the same weight)
+//   mono  the 14 monomials of representative p (the opposite's odd ones
+//         change sign)
+//   nu    c dt / dx of representative p along x and y (Courant numbers)
+template <typename C>
+struct GHConsts {
+  C w[D2Q36GH::P];
+  C mono[D2Q36GH::P][GH_MONO];
+  C nu[D2Q36GH::P][2];
+};
+
+// Raw moments sum w h (1, c, cc, ccc) of the deviational h over the set,
+// from the (alpha, alpha + P) pair sums and differences.
+template <typename C>
+__device__ __forceinline__ void raw_moments_gh(const C (&h)[D2Q36GH::Q], const GHConsts<C>* __restrict__ g,
+                                               bool third, RawMoments<D2Q36GH, C>& m) {
+  constexpr int P = D2Q36GH::P;
+  m.drho = C(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    m.J[i] = C(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      m.S2[i][j] = C(0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) m.S3[i][j][k] = C(0);
+    }
+  }
+  C s111 = C(0), s112 = C(0), s122 = C(0), s222 = C(0);
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const C* mo = g->mono[p];
+    const C ws = g->w[p] * (h[p] + h[p + P]);
+    const C wd = g->w[p] * (h[p] - h[p + P]);
+    m.drho += ws;
+    m.J[0] = fmac(wd, mo[0], m.J[0]);
+    m.J[1] = fmac(wd, mo[1], m.J[1]);
+    m.S2[0][0] = fmac(ws, mo[2], m.S2[0][0]);
+    m.S2[0][1] = fmac(ws, mo[3], m.S2[0][1]);
+    m.S2[1][1] = fmac(ws, mo[4], m.S2[1][1]);
+    if (third) {
+      s111 = fmac(wd, mo[5], s111);
+      s112 = fmac(wd, mo[6], s112);
+      s122 = fmac(wd, mo[7], s122);
+      s222 = fmac(wd, mo[8], s222);
+    }
+  }
+  m.S2[1][0] = m.S2[0][1];
+  if (third) {
+    m.S3[0][0][0] = s111;
+    m.S3[0][0][1] = m.S3[0][1][0] = m.S3[1][0][0] = s112;
+    m.S3[0][1][1] = m.S3[1][0][1] = m.S3[1][1][0] = s122;
+    m.S3[1][1][1] = s222;
+  }
+}
+
+// Forward-Euler collision and force of the scheme (Sec. 3.1) in place:
+// h* = h - omega (h - h_ES) + dt F/w, with omega = dt/tau and the ES and
+// force coefficients of Sec. 2.2 from the moments of h. lc carries r = 1
+// (the velocities are the abscissae themselves); pp has hs = hsdt = 0.
+template <typename C>
+__device__ __forceinline__ void collide_gh(C (&h)[D2Q36GH::Q], const GHConsts<C>* __restrict__ g,
+                                           const LatConsts<C>* __restrict__ lc,
+                                           const ProbParams<C>* __restrict__ pp) {
+  using L = D2Q36GH;
+  constexpr int P = L::P;
+  RawMoments<L, C> m;
+  raw_moments_gh<C>(h, g, pp->force != 0, m);
+  CellState<L, C> s;
+  reconstruct<L, C>(m, lc, pp, s);
+  C K0, K1[3], K2[3][3], K3[3][3][3], K4[3][3][3][3];
+  poly_coeffs<L, C>(m, s, lc, pp, K0, K1, K2, K3, K4);
+  // coefficients of the monomials (with their multiplicities)
+  const C k2[3] = {K2[0][0], C(2) * K2[0][1], K2[1][1]};
+  const C k3[4] = {K3[0][0][0], C(3) * K3[0][0][1], C(3) * K3[0][1][1], K3[1][1][1]};
+  const C k4[5] = {K4[0][0][0][0], C(4) * K4[0][0][0][1], C(6) * K4[0][0][1][1], C(4) * K4[0][1][1][1],
+                   K4[1][1][1][1]};
+  const C omw = C(1) - s.omega;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const C* mo = g->mono[p];
+    C E = K0, O = C(0);
+    O = fmac(K1[0], mo[0], O);
+    O = fmac(K1[1], mo[1], O);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) E = fmac(k2[k], mo[2 + k], E);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) O = fmac(k3[k], mo[5 + k], O);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) E = fmac(k4[k], mo[9 + k], E);
+    const C hp = fmac(omw, h[p], E + O);
+    const C hm = fmac(omw, h[p + P], E - O);
+    h[p] = hp;
+    h[p + P] = hm;
+  }
+}
+
+// rho, u[2], T, sigma (xx, xy, yy), q[2] of the stored (physical) f.
+template <typename C>
+__device__ __forceinline__ void cell_fields_gh(const C (&h)[D2Q36GH::Q], const GHConsts<C>* __restrict__ g,
+                                               const LatConsts<C>* __restrict__ lc,
+                                               const ProbParams<C>* __restrict__ pp, double* out) {
+  using L = D2Q36GH;
+  constexpr int D = 2;
+  RawMoments<L, C> m;
+  raw_moments_gh<C>(h, g, true, m);
+  CellState<L, C> s;
+  reconstruct<L, C>(m, lc, pp, s);
+  C A3[3][3][3], a2[3][3], a3[3][3][3];
+  es3_and_a2<L, C>(s, A3, a2);
+  physical_a3<L, C>(m, s, A3, a2, lc->r, pp->hs, pp->g, pp->force != 0, a3);
+  int f = 0;
+  out[f++] = 1.0 + double(s.drho);
+#pragma unroll
+  for (int i = 0; i < D; ++i) out[f++] = double(s.u[i]);
+  out[f++] = 1.0 + double(s.theta);
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = i; j < D; ++j) out[f++] = double(s.sigma[i][j]);
+  C uu = C(0), tra2 = C(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) { uu += s.u[i] * s.u[i]; tra2 += a2[i][i]; }
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    C t3 = C(0), au = C(0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) { t3 += a3[i][j][j]; au += a2[i][j] * s.u[j]; }
+    out[f++] = double(C(0.5) * (t3 - s.u[i] * tra2 - C(2) * au + C(2) * s.rho * s.u[i] * uu));
+  }
+}
+
+// minmod(a, b): 0 unless a and b share a sign, else the one smaller in
+// magnitude; equals a Psi(b / a) with the limiter Psi of Sec. 3.1.
+template <typename C>
+__device__ __forceinline__ C minmod(C a, C b) {
+  const C m = (b < C(0) ? -b : b) < (a < C(0) ? -a : a) ? b : a;
+  return a * b > C(0) ? m : C(0);
+}
+
+// Flux difference nu (F_{i+1/2} - F_{i-1/2}) of one velocity along one axis
+// (Sec. 3.1) from the stencil values fm2 .. fp2 (f_{i-2} .. f_{i+2}); only
+// the upwind-biased four of them are used.
+template <typename C>
+__device__ __forceinline__ C tvd_difference(bool positive, C nu, C fm2, C fm1, C f0, C fp1, C fp2) {
+  if (positive) {
+    const C k = C(0.5) * (C(1) - nu);
+    const C Fr = f0 + k * minmod(fp1 - f0, f0 - fm1);
+    const C Fl = fm1 + k * minmod(f0 - fm1, fm1 - fm2);
+    return nu * (Fr - Fl);
+  }
+  const C k = C(0.5) * (C(1) + nu);     // 1 - |nu|
+  const C Fr = fp1 - k * minmod(fp1 - f0, fp2 - fp1);
+  const C Fl = f0 - k * minmod(f0 - fm1, fp1 - f0);
+  return nu * (Fr - Fl);
+}
+
+}  // namespace esbgk

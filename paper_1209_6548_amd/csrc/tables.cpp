@@ -23,6 +23,7 @@
 #include "lattice.h"
 #include "params.h"
 #include "tables.h"
+#include "gh.h"
 
 namespace esbgk {
 
@@ -246,6 +247,85 @@ const HostLattice* host_lattice(int velset) {
     }
   });
   return ok[i] ? &lat[i] : nullptr;
+}
+
+// 1-D rule of eq. weight: the n roots of the probabilists' Hermite polynomial
+// He_n (recurrence He_{k+1} = x He_k - k He_{k-1}), located by a sign scan of
+// (-sqrt(4n+2), sqrt(4n+2)) and bisection in long double, and the weights
+// n! / [n He_{n-1}(x)]^2.
+static bool gauss_hermite_rule(int n, std::vector<ld>& x, std::vector<ld>& w) {
+  auto he = [](int k, ld t) {
+    ld a = 1, b = t;
+    if (k == 0) return a;
+    for (int j = 1; j < k; ++j) {
+      const ld c = t * b - ld(j) * a;
+      a = b;
+      b = c;
+    }
+    return b;
+  };
+  const ld lim = std::sqrt(ld(4 * n + 2));
+  const int scan = 40000;
+  x.clear();
+  ld prev_t = -lim, prev_v = he(n, -lim);
+  for (int k = 1; k <= scan; ++k) {
+    const ld t = -lim + 2 * lim * ld(k) / ld(scan);
+    const ld v = he(n, t);
+    if ((prev_v < 0) != (v < 0)) {
+      ld lo = prev_t, hi = t, vlo = prev_v;
+      for (int it = 0; it < 200; ++it) {
+        const ld mid = 0.5L * (lo + hi), vm = he(n, mid);
+        if ((vm < 0) == (vlo < 0)) {
+          lo = mid;
+          vlo = vm;
+        } else {
+          hi = mid;
+        }
+      }
+      x.push_back(0.5L * (lo + hi));
+    }
+    prev_t = t;
+    prev_v = v;
+  }
+  if (int(x.size()) != n) return false;
+  ld fact = 1;
+  for (int k = 2; k <= n; ++k) fact *= k;
+  w.resize(n);
+  for (int k = 0; k < n; ++k) {
+    const ld h = ld(n) * he(n - 1, x[k]);
+    w[k] = fact / (h * h);
+  }
+  return true;
+}
+
+const HostGH* host_gh() {
+  static HostGH gh;
+  static bool ok = false;
+  static std::once_flag once;
+  std::call_once(once, [&]() {
+    std::vector<ld> x, w;
+    if (!gauss_hermite_rule(6, x, w)) return;
+    // symmetric rule: positive roots x[3..5]; rank k in {+-1,+-2,+-3} means
+    // sign(k) * xi[|k| - 1]
+    ld xi[3], w1[3];
+    for (int m = 0; m < 3; ++m) {
+      xi[m] = 0.5L * (x[3 + m] - x[2 - m]);   // average the mirrored pair
+      w1[m] = 0.5L * (w[3 + m] + w[2 - m]);
+      gh.xi[m] = double(xi[m]);
+    }
+    for (int a = 0; a < 36; ++a) {
+      ld wa = 1;
+      for (int i = 0; i < 2; ++i) {
+        const int k = D2Q36GH::K[a % 18][i] * (a < 18 ? 1 : -1);
+        const int m = (k < 0 ? -k : k) - 1;
+        gh.c[a][i] = double(k < 0 ? -xi[m] : xi[m]);
+        wa *= w1[m];
+      }
+      gh.w[a] = double(wa);
+    }
+    ok = true;
+  });
+  return ok ? &gh : nullptr;
 }
 
 // S(T, u)(c_alpha) / w_alpha - 1: eq. feq0 with rho = 1, truncated at order N.

@@ -19,6 +19,17 @@ struct HostLattice {
 // Derived once per process; null if the derivation failed.
 const HostLattice* host_lattice(int velset);
 
+// The 6-point Gauss-Hermite product set D2Q36 of the paper's own scheme:
+// positive roots xi[0..2] of He_6 (ascending), and per velocity (in the order
+// of D2Q36GH) the abscissae c[a][2] and weights w[a]. Derived once per
+// process; null if the derivation failed.
+struct HostGH {
+  double xi[3];
+  double c[36][2];
+  double w[36];
+};
+const HostGH* host_gh();
+
 // S(T, u)/w - 1 at velocity a (eq. feq0, rho = 1, order N of the lattice).
 double shat_minus_one(const HostLattice& lat, int a, double T, const double u[3]);
 

@@ -1,0 +1,196 @@
+// Kernels of the paper's own scheme (Sec. 3.1) on the 6-point Gauss-Hermite
+// product set D2Q36: one fused launch per step computes, per cell and
+// velocity, the TVD minmod flux difference along x and y from the five-cell
+// stencil of the stored level and the forward-Euler ES-BGK collision and
+// force from the cell's own populations, and writes
+//   h^{n+1} = h^n - omega (h^n - h_ES) + dt F/w - nu_x [...] - nu_y [...].
+// Periodic in both axes. Populations use the slice layout of Geometry (slice
+// = row y); a wavefront shares its row, so the rows y-2..y+2 are scalar
+// buffer resources and only the x offsets are per lane.
+
+#include <hip/hip_runtime.h>
+
+#include "gh.h"
+#include "stream.h"
+#include "tvd.h"
+
+namespace esbgk {
+
+namespace {
+
+constexpr uint32_t BLOCK = 256;
+
+template <typename S>
+struct StepT2 {
+  using type = float;
+};
+template <>
+struct StepT2<double> {
+  using type = double;
+};
+
+__device__ __forceinline__ uint32_t xcd_block2(uint32_t b, uint32_t nb) {
+  const uint32_t per = nb >> 3;
+  if (b < (per << 3)) return (b & 7u) * per + (b >> 3);
+  return b;
+}
+
+}  // namespace
+
+template <typename S>
+__global__ void __launch_bounds__(BLOCK)
+k_tvd(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
+      const GHConsts<typename StepT2<S>::type>* __restrict__ gc,
+      const LatConsts<typename StepT2<S>::type>* __restrict__ lc,
+      const ProbParams<typename StepT2<S>::type>* __restrict__ pp) {
+  using C = typename StepT2<S>::type;
+  using L = D2Q36GH;
+  constexpr int Q = L::Q, P = L::P;
+  constexpr uint32_t ss = sizeof(S);
+  const uint32_t blk = xcd_block2(blockIdx.x, gridDim.x);
+  const uint32_t wave0 = blk * BLOCK + (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u);
+  const uint32_t s = __builtin_amdgcn_readfirstlane(fdiv(wave0, geo.div_ipad));
+  const uint32_t x = blk * BLOCK + threadIdx.x - s * geo.ipad;
+  if (s >= geo.nslices || x >= geo.inner) return;
+  const uint32_t bb = geo.sstride * ss, pb = geo.pstride * ss;
+  const int ns = int(geo.nslices), nx = int(geo.nx);
+  Rsrc row[5];
+#pragma unroll
+  for (int k = -2; k <= 2; ++k)
+    row[k + 2] = block_rsrc(reinterpret_cast<const char*>(src) + size_t(wrapc(int(s) + k, ns)) * bb, bb);
+  uint32_t xo[5];
+#pragma unroll
+  for (int k = -2; k <= 2; ++k) xo[k + 2] = uint32_t(wrapc(int(x) + k, nx)) * ss;
+
+  // collision of the cell's own populations first (36 loads), then the flux
+  // differences velocity by velocity; scheduling barriers between groups of
+  // velocities keep the compiler from hoisting all 252 stencil loads at
+  // once (which would need far more than 128 VGPRs)
+  C h[Q];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) h[a] = widen<C, S>(buf_ld<S>(row[2], xo[2], uint32_t(a) * pb));
+  collide_gh<C>(h, gc, lc, pp);
+  const Rsrc out = block_rsrc(reinterpret_cast<char*>(dst) + size_t(s) * bb, bb);
+  constexpr int G = 4;   // velocities per group
+#pragma unroll
+  for (int a0 = 0; a0 < Q; a0 += G) {
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int a = a0; a < a0 + G && a < Q; ++a) {
+      const uint32_t po = uint32_t(a) * pb;
+      const int p = a % P;
+      const C sg = a < P ? C(1) : C(-1);
+      const bool px = gh_sign(a, 0) > 0, py = gh_sign(a, 1) > 0;
+      const C f0 = widen<C, S>(buf_ld<S>(row[2], xo[2], po));
+      const C xm1 = widen<C, S>(buf_ld<S>(row[2], xo[1], po));
+      const C xp1 = widen<C, S>(buf_ld<S>(row[2], xo[3], po));
+      const C x2 = widen<C, S>(buf_ld<S>(row[2], px ? xo[0] : xo[4], po));
+      const C ym1 = widen<C, S>(buf_ld<S>(row[1], xo[2], po));
+      const C yp1 = widen<C, S>(buf_ld<S>(row[3], xo[2], po));
+      const C y2 = widen<C, S>(buf_ld<S>(py ? row[0] : row[4], xo[2], po));
+      const C nux = sg * gc->nu[p][0], nuy = sg * gc->nu[p][1];
+      const C dx = px ? tvd_difference<C>(true, nux, x2, xm1, f0, xp1, C(0))
+                      : tvd_difference<C>(false, nux, C(0), xm1, f0, xp1, x2);
+      const C dy = py ? tvd_difference<C>(true, nuy, y2, ym1, f0, yp1, C(0))
+                      : tvd_difference<C>(false, nuy, C(0), ym1, f0, yp1, y2);
+      buf_st<S>(narrow<S, C>(h[a] - (dx + dy)), out, x * ss, po);
+    }
+  }
+}
+
+// h = rho S(T, u)/w (1 + amp xi) - 1 for cells [c0, c0 + count) (eq. feq0 at
+// N = 4 with the abscissae c[Q][2]); fields [count] / [2][count] / [Q][count]
+// or null.
+template <typename S>
+__global__ void __launch_bounds__(BLOCK)
+k_tvd_init(Geometry geo, S* __restrict__ dst, const double* __restrict__ c, const double* __restrict__ rho,
+           const double* __restrict__ u, const double* __restrict__ T, const double* __restrict__ noise, double amp,
+           uint32_t c0, uint32_t count) {
+  const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t cell = c0 + i;
+  const uint32_t y = cell / geo.nx, x = cell - y * geo.nx;
+  const size_t elem = size_t(y) * geo.sstride + x;
+  const double drho = rho ? rho[i] - 1.0 : 0.0;
+  const double ux = u ? u[i] : 0.0, uy = u ? u[size_t(count) + i] : 0.0;
+  const double th = T ? T[i] - 1.0 : 0.0;
+  const double uu = ux * ux + uy * uy;
+  for (int a = 0; a < D2Q36GH::Q; ++a) {
+    const double cx = c[2 * a], cy = c[2 * a + 1];
+    const double cu = cx * ux + cy * uy, cc = cx * cx + cy * cy;
+    double sm1 = cu + 0.5 * (cu * cu - uu + th * (cc - 2.0)) + cu / 6.0 * (cu * cu - 3.0 * uu + 3.0 * th * (cc - 4.0));
+    sm1 += (cu * cu * cu * cu - 6.0 * cu * cu * uu + 3.0 * uu * uu) / 24.0 +
+           th / 4.0 * ((cc - 4.0) * (cu * cu - uu) - 2.0 * cu * cu) + th * th / 8.0 * (cc * cc - 8.0 * cc + 8.0);
+    double hv = drho * (1.0 + sm1) + sm1;
+    if (noise) hv += (1.0 + hv) * amp * noise[size_t(a) * count + i];
+    dst[size_t(a) * geo.pstride + elem] = S(hv);
+  }
+}
+
+// Fields of cells [c0, c0 + count) from their own stored populations (FP64
+// arithmetic), written as [9][count].
+template <typename S>
+__global__ void __launch_bounds__(BLOCK)
+k_tvd_moments(Geometry geo, const S* __restrict__ src, const GHConsts<double>* __restrict__ gc,
+              const LatConsts<double>* __restrict__ lc, const ProbParams<double>* __restrict__ pp, uint32_t c0,
+              uint32_t count, double* __restrict__ out) {
+  const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t cell = c0 + i;
+  const uint32_t y = cell / geo.nx, x = cell - y * geo.nx;
+  const size_t elem = size_t(y) * geo.sstride + x;
+  double h[D2Q36GH::Q];
+  for (int a = 0; a < D2Q36GH::Q; ++a) h[a] = double(src[size_t(a) * geo.pstride + elem]);
+  double f[9];
+  cell_fields_gh<double>(h, gc, lc, pp, f);
+  for (int k = 0; k < 9; ++k) out[size_t(k) * count + i] = f[k];
+}
+
+#define ESBGK_TVD_DISPATCH(storage, CALL)                  \
+  do {                                                     \
+    if (storage == 0) { using S = double; return CALL; }   \
+    if (storage == 1) { using S = float; return CALL; }    \
+    if (storage == 2) { using S = _Float16; return CALL; } \
+    return hipErrorInvalidValue;                           \
+  } while (0)
+
+template <typename S>
+static hipError_t tvd_step_t(const TVDArgs& a) {
+  using C = typename StepT2<S>::type;
+  const uint32_t nb = uint32_t((uint64_t(a.geo.nslices) * a.geo.ipad + BLOCK - 1) / BLOCK);
+  hipLaunchKernelGGL(k_tvd<S>, dim3(nb), dim3(BLOCK), 0, a.stream, a.geo, static_cast<const S*>(a.src),
+                     static_cast<S*>(a.dst), static_cast<const GHConsts<C>*>(a.gc),
+                     static_cast<const LatConsts<C>*>(a.lc), static_cast<const ProbParams<C>*>(a.pp));
+  return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t tvd_init_t(const TVDArgs& a, const double* c, const double* rho, const double* u,
+                             const double* T, const double* noise, double amp, uint32_t c0, uint32_t count) {
+  const uint32_t nb = (count + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL(k_tvd_init<S>, dim3(nb), dim3(BLOCK), 0, a.stream, a.geo, static_cast<S*>(a.dst), c, rho, u,
+                     T, noise, amp, c0, count);
+  return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t tvd_moments_t(const TVDArgs& a, uint32_t c0, uint32_t count, double* out) {
+  const uint32_t nb = (count + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL(k_tvd_moments<S>, dim3(nb), dim3(BLOCK), 0, a.stream, a.geo, static_cast<const S*>(a.src),
+                     static_cast<const GHConsts<double>*>(a.gc64), static_cast<const LatConsts<double>*>(a.lc64),
+                     static_cast<const ProbParams<double>*>(a.pp64), c0, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_tvd_step(int storage, const TVDArgs& a) { ESBGK_TVD_DISPATCH(storage, tvd_step_t<S>(a)); }
+
+hipError_t launch_tvd_init(int storage, const TVDArgs& a, const double* c, const double* rho, const double* u,
+                           const double* T, const double* noise, double amp, uint32_t c0, uint32_t count) {
+  ESBGK_TVD_DISPATCH(storage, (tvd_init_t<S>(a, c, rho, u, T, noise, amp, c0, count)));
+}
+
+hipError_t launch_tvd_moments(int storage, const TVDArgs& a, uint32_t c0, uint32_t count, double* out) {
+  ESBGK_TVD_DISPATCH(storage, (tvd_moments_t<S>(a, c0, count, out)));
+}
+
+}  // namespace esbgk
