@@ -11,7 +11,9 @@ Printed: one JSON line with MLUPS (the metric), the roofline of the step
 kernel (algorithmic bytes 2 Q s per cell update / measured kernel time
 against the 8 TB/s HBM peak), the same workload with plain FP64 and with
 FP16 storage, the batched-channel workload in one persistent launch against
-a per-problem FP64 loop, and the FP64 CPU oracle timed on a bounded sample.
+a per-problem FP64 loop, 3-D workloads, the paper's own TVD scheme on the
+6-point Gauss-Hermite set (1024 x 1024, FP32 and FP64), and the FP64 CPU
+oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--only-main]
 """
@@ -74,6 +76,32 @@ def bench_single(cfg, storage, steps, warmup):
                algorithmic_GBs=bytes_per_step / (ms * 1e-3) / 1e9, bytes_per_cell=2 * lat.Q * s)
     red = lat.reduce()
     out["finite"] = bool(np.isfinite(red["mass"]) and np.isfinite(red["energy"]))
+    lat.close()
+    return out
+
+
+TVD_CFG = dict(name="periodic_gas_1024x1024_d2q36", dims=(1024, 1024), Kn=0.05, Pr=2 / 3, cfl=0.5)
+
+
+def bench_tvd(storage, steps, warmup):
+    """The paper's own scheme (forward Euler, TVD minmod fluxes) on the
+    6-point Gauss-Hermite product set D2Q36, 1024 x 1024 periodic cells,
+    from a perturbed equilibrium (the kernel's work does not depend on the
+    state: the limiter branches are selects)."""
+    from paper_1209_6548_amd import TVDLattice
+    nx, ny = TVD_CFG["dims"]
+    lat = TVDLattice(nx, ny, storage=storage, cfl=TVD_CFG["cfl"])
+    lat.set_gas(TVD_CFG["Kn"], TVD_CFG["Pr"])
+    lat.set_body_force((1e-3, 0.0))
+    rng = np.random.default_rng(1)
+    lat.init_equilibrium(noise=rng.standard_normal((36, nx * ny)), amplitude=1e-3)
+    ms = time_steps(lat, steps, warmup)
+    cells = nx * ny
+    s = {"f64": 8, "f32": 4, "f16": 2}[storage]
+    m = lat.read_moments()
+    out = dict(workload=TVD_CFG["name"], storage=storage, ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6,
+               algorithmic_GBs=2 * 36 * s * cells / (ms * 1e-3) / 1e9, bytes_per_cell=2 * 36 * s,
+               kernel=f"k_tvd<{storage}>", finite=bool(np.isfinite(m["rho"]).all()))
     lat.close()
     return out
 
@@ -232,6 +260,9 @@ def main():
                          "the FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--storage", default="f32", choices=("f32", "f64", "f16"),
                     help="storage of the headline run (default f32)")
+    ap.add_argument("--kernel", default="step", choices=("step", "tvd"),
+                    help="with --profile: the kernel to run after the calibration copy (step: the headline "
+                         "lattice step; tvd: the paper's own TVD scheme on D2Q36)")
     args = ap.parse_args()
     if args.profile:
         args.only_main, args.no_cpu = True, True
@@ -255,6 +286,11 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 1073741824 bytes read, 1073741824 bytes written")
         del a, b
+        if args.kernel == "tvd":
+            t = bench_tvd(args.storage, args.steps, args.warmup)
+            log(f"tvd {args.storage}: {t['mlups']:.0f} MLUPS, {t['algorithmic_GBs']:.0f} GB/s")
+            print(json.dumps(t), flush=True)
+            return
     log(f"headline: {cfg['name']} {args.storage}, {args.steps} steps after {args.warmup} warmup")
     main_run = bench_single(cfg, args.storage, args.steps, args.warmup)
     log(f"{args.storage}: {main_run['mlups']:.0f} MLUPS, {main_run['algorithmic_GBs']:.0f} GB/s")
@@ -277,6 +313,10 @@ def main():
         key = f"{ch['name']}_f16"
         variants[key] = bench_single(ch, "f16", max(10, args.steps // 10), 3)
         log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
+        for st in ("f32", "f64"):
+            key = f"{TVD_CFG['name']}_{st}"
+            variants[key] = bench_tvd(st, max(20, args.steps // 2), 5)
+            log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
     copy_gbs = None
     if not args.only_main:
         copy_gbs = copy_bandwidth()

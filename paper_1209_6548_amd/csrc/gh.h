@@ -41,12 +41,16 @@ constexpr int GH_MONO = 14;
 //   w     weight of representative p (its opposite has the same weight)
 //   mono  the 14 monomials of representative p (the opposite's odd ones
 //         change sign)
-//   nu    c dt / dx of representative p along x and y (Courant numbers)
+//   nu    c dt / dx of representative p along x and y (Courant numbers;
+//         the opposite velocity has -nu)
+//   nk    |nu| (1 - |nu|) / 2, the weight of the limited slopes in the
+//         flux difference (the same for the opposite velocity)
 template <typename C>
 struct GHConsts {
   C w[D2Q36GH::P];
   C mono[D2Q36GH::P][GH_MONO];
   C nu[D2Q36GH::P][2];
+  C nk[D2Q36GH::P][2];
 };
 
 // Raw moments sum w h (1, c, cc, ccc) of the deviational h over the set,
@@ -94,45 +98,75 @@ __device__ __forceinline__ void raw_moments_gh(const C (&h)[D2Q36GH::Q], const G
   }
 }
 
-// Forward-Euler collision and force of the scheme (Sec. 3.1) in place:
+// Forward-Euler collision and force of the scheme (Sec. 3.1):
 // h* = h - omega (h - h_ES) + dt F/w, with omega = dt/tau and the ES and
 // force coefficients of Sec. 2.2 from the moments of h. lc carries r = 1
 // (the velocities are the abscissae themselves); pp has hs = hsdt = 0.
+// h_ES + dt F/w is a polynomial of degree 4 in c; GHCollision holds its
+// coefficients per monomial (multiplicities folded in) and 1 - omega, so
+// that the pair (p, p + P) follows from its even and odd parts.
 template <typename C>
-__device__ __forceinline__ void collide_gh(C (&h)[D2Q36GH::Q], const GHConsts<C>* __restrict__ g,
-                                           const LatConsts<C>* __restrict__ lc,
-                                           const ProbParams<C>* __restrict__ pp) {
+struct GHCollision {
+  C K0, K1[2], k2[3], k3[4], k4[5], omw;
+};
+
+template <typename C>
+__device__ __forceinline__ void collision_gh(const C (&h)[D2Q36GH::Q], const GHConsts<C>* __restrict__ g,
+                                             const LatConsts<C>* __restrict__ lc,
+                                             const ProbParams<C>* __restrict__ pp, GHCollision<C>& k) {
   using L = D2Q36GH;
-  constexpr int P = L::P;
   RawMoments<L, C> m;
   raw_moments_gh<C>(h, g, pp->force != 0, m);
   CellState<L, C> s;
   reconstruct<L, C>(m, lc, pp, s);
   C K0, K1[3], K2[3][3], K3[3][3][3], K4[3][3][3][3];
   poly_coeffs<L, C>(m, s, lc, pp, K0, K1, K2, K3, K4);
-  // coefficients of the monomials (with their multiplicities)
-  const C k2[3] = {K2[0][0], C(2) * K2[0][1], K2[1][1]};
-  const C k3[4] = {K3[0][0][0], C(3) * K3[0][0][1], C(3) * K3[0][1][1], K3[1][1][1]};
-  const C k4[5] = {K4[0][0][0][0], C(4) * K4[0][0][0][1], C(6) * K4[0][0][1][1], C(4) * K4[0][1][1][1],
-                   K4[1][1][1][1]};
-  const C omw = C(1) - s.omega;
+  k.K0 = K0;
+  k.K1[0] = K1[0];
+  k.K1[1] = K1[1];
+  k.k2[0] = K2[0][0];
+  k.k2[1] = C(2) * K2[0][1];
+  k.k2[2] = K2[1][1];
+  k.k3[0] = K3[0][0][0];
+  k.k3[1] = C(3) * K3[0][0][1];
+  k.k3[2] = C(3) * K3[0][1][1];
+  k.k3[3] = K3[1][1][1];
+  k.k4[0] = K4[0][0][0][0];
+  k.k4[1] = C(4) * K4[0][0][0][1];
+  k.k4[2] = C(6) * K4[0][0][1][1];
+  k.k4[3] = C(4) * K4[0][1][1][1];
+  k.k4[4] = K4[1][1][1][1];
+  k.omw = C(1) - s.omega;
+}
+
+// Post-collision values of the pair (p, p + P) from their pre-collision
+// values hp, hm.
+template <typename C>
+__device__ __forceinline__ void collide_pair_gh(const GHCollision<C>& k, const C* __restrict__ mo, C hp, C hm,
+                                                C& outp, C& outm) {
+  C E = k.K0, O = C(0);
+  O = fmac(k.K1[0], mo[0], O);
+  O = fmac(k.K1[1], mo[1], O);
 #pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const C* mo = g->mono[p];
-    C E = K0, O = C(0);
-    O = fmac(K1[0], mo[0], O);
-    O = fmac(K1[1], mo[1], O);
+  for (int j = 0; j < 3; ++j) E = fmac(k.k2[j], mo[2 + j], E);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) E = fmac(k2[k], mo[2 + k], E);
+  for (int j = 0; j < 4; ++j) O = fmac(k.k3[j], mo[5 + j], O);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) O = fmac(k3[k], mo[5 + k], O);
+  for (int j = 0; j < 5; ++j) E = fmac(k.k4[j], mo[9 + j], E);
+  outp = fmac(k.omw, hp, E + O);
+  outm = fmac(k.omw, hm, E - O);
+}
+
+// The collision of every velocity in place.
+template <typename C>
+__device__ __forceinline__ void collide_gh(C (&h)[D2Q36GH::Q], const GHConsts<C>* __restrict__ g,
+                                           const LatConsts<C>* __restrict__ lc,
+                                           const ProbParams<C>* __restrict__ pp) {
+  constexpr int P = D2Q36GH::P;
+  GHCollision<C> k;
+  collision_gh<C>(h, g, lc, pp, k);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) E = fmac(k4[k], mo[9 + k], E);
-    const C hp = fmac(omw, h[p], E + O);
-    const C hm = fmac(omw, h[p + P], E - O);
-    h[p] = hp;
-    h[p + P] = hm;
-  }
+  for (int p = 0; p < P; ++p) collide_pair_gh<C>(k, g->mono[p], h[p], h[p + P], h[p], h[p + P]);
 }
 
 // rho, u[2], T, sigma (xx, xy, yy), q[2] of the stored (physical) f.
@@ -171,28 +205,30 @@ __device__ __forceinline__ void cell_fields_gh(const C (&h)[D2Q36GH::Q], const G
 }
 
 // minmod(a, b): 0 unless a and b share a sign, else the one smaller in
-// magnitude; equals a Psi(b / a) with the limiter Psi of Sec. 3.1.
-template <typename C>
-__device__ __forceinline__ C minmod(C a, C b) {
-  const C m = (b < C(0) ? -b : b) < (a < C(0) ? -a : a) ? b : a;
-  return a * b > C(0) ? m : C(0);
+// magnitude; equals a Psi(b / a) with the limiter Psi of Sec. 3.1 and the
+// median of (a, b, 0), which is one instruction (v_med3_f32) in FP32.
+__device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
+__device__ __forceinline__ double minmod(double a, double b) {
+  return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
 }
 
-// Flux difference nu (F_{i+1/2} - F_{i-1/2}) of one velocity along one axis
-// (Sec. 3.1) from the stencil values fm2 .. fp2 (f_{i-2} .. f_{i+2}); only
-// the upwind-biased four of them are used.
+// The flux difference nu (F_{i+1/2} - F_{i-1/2}) of one velocity along one
+// axis (Sec. 3.1) is nu d + nk m, with nk = |nu| (1 - |nu|) / 2, d the
+// upwind difference (f_i - f_{i-1} for nu > 0, f_{i+1} - f_i for nu < 0)
+// and m the difference of the limited slopes at the right and left faces
+// (for nu < 0 the paper's formula mirrored). The stencil is the four
+// upwind-biased values: f2 = f_{i-2} for nu > 0, f2 = f_{i+2} for nu < 0.
 template <typename C>
-__device__ __forceinline__ C tvd_difference(bool positive, C nu, C fm2, C fm1, C f0, C fp1, C fp2) {
+__device__ __forceinline__ void tvd_terms(bool positive, C f2, C fm1, C f0, C fp1, C& d, C& m) {
   if (positive) {
-    const C k = C(0.5) * (C(1) - nu);
-    const C Fr = f0 + k * minmod(fp1 - f0, f0 - fm1);
-    const C Fl = fm1 + k * minmod(f0 - fm1, fm1 - fm2);
-    return nu * (Fr - Fl);
+    const C dm = fm1 - f2, d0 = f0 - fm1, dp = fp1 - f0;
+    d = d0;
+    m = minmod(dp, d0) - minmod(d0, dm);
+  } else {
+    const C dm = f0 - fm1, d0 = fp1 - f0, dp = f2 - fp1;
+    d = d0;
+    m = minmod(d0, dp) - minmod(dm, d0);
   }
-  const C k = C(0.5) * (C(1) + nu);     // 1 - |nu|
-  const C Fr = fp1 - k * minmod(fp1 - f0, fp2 - fp1);
-  const C Fl = f0 - k * minmod(f0 - fm1, fp1 - f0);
-  return nu * (Fr - Fl);
 }
 
 }  // namespace esbgk

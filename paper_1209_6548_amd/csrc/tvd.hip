@@ -37,6 +37,72 @@ __device__ __forceinline__ uint32_t xcd_block2(uint32_t b, uint32_t nb) {
 
 }  // namespace
 
+// Value of lane i - 1 (shr) or i + 1 (shl) of the wavefront; the lane
+// whose source is off the wavefront (lane 0, lane 63) keeps its `old`.
+__device__ __forceinline__ int dpp_shift(int old, int v, bool right) {
+  return right ? __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false)    // wave_shr:1
+               : __builtin_amdgcn_update_dpp(old, v, 0x130, 0xf, 0xf, false);   // wave_shl:1
+}
+__device__ __forceinline__ float lane_shift(float old, float v, bool right) {
+  return __builtin_bit_cast(float, dpp_shift(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v), right));
+}
+__device__ __forceinline__ double lane_shift(double old, double v, bool right) {
+  const uint64_t o = __builtin_bit_cast(uint64_t, old), w = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = uint32_t(dpp_shift(int(uint32_t(o)), int(uint32_t(w)), right));
+  const uint32_t hi = uint32_t(dpp_shift(int(uint32_t(o >> 32)), int(uint32_t(w >> 32)), right));
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
+__device__ __forceinline__ int posmod(int v, int n) { return ((v % n) + n) % n; }
+
+// The advection and collision of every velocity of one cell, writing
+// h* - nu_x [...] - nu_y [...]. h holds the cell's level-n populations.
+// Lane i of the wavefront holds cell (x0 + i) mod nx of its row, so the x
+// neighbours of lanes 1..62 are the neighbouring lanes' registers; the
+// halo load of each velocity brings (x0 - 1, x0 - 2, x0 + 65, x0 + 64)
+// mod nx into lanes (0, 1, 62, 63) for the rest.
+template <typename S, typename C>
+__device__ __forceinline__ void tvd_cell(const C (&h)[D2Q36GH::Q], const GHCollision<C>& k,
+                                         const GHConsts<C>* __restrict__ gc, const Rsrc (&row)[5], uint32_t xo,
+                                         uint32_t hoff, uint32_t so, uint32_t pb, const Rsrc out) {
+  using L = D2Q36GH;
+  constexpr int P = L::P;
+  constexpr int G = 2;   // velocity pairs per scheduling group
+#pragma unroll
+  for (int p0 = 0; p0 < P; p0 += G) {
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int p = p0; p < p0 + G && p < P; ++p) {
+      C hs[2];
+      collide_pair_gh<C>(k, gc->mono[p], h[p], h[p + P], hs[0], hs[1]);
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int a = p + side * P;
+        const uint32_t po = uint32_t(a) * pb;
+        const bool px = gh_sign(a, 0) > 0, py = gh_sign(a, 1) > 0;
+        const C sg = side == 0 ? C(1) : C(-1);
+        const C f0 = h[a];
+        const C H = widen<C, S>(buf_ld<S>(row[2], hoff, po));
+        const C xm1 = lane_shift(H, f0, true);
+        const C xp1 = lane_shift(H, f0, false);
+        const C x2 = px ? lane_shift(lane_shift(H, H, false), xm1, true)     // lane 0 takes x0 - 2
+                        : lane_shift(lane_shift(H, H, true), xp1, false);    // lane 63 takes x0 + 65
+        const C ym1 = widen<C, S>(buf_ld<S>(row[1], xo, po));
+        const C yp1 = widen<C, S>(buf_ld<S>(row[3], xo, po));
+        const C y2 = widen<C, S>(buf_ld<S>(py ? row[0] : row[4], xo, po));
+        C dx, mx, dy, my;
+        tvd_terms<C>(px, x2, xm1, f0, xp1, dx, mx);
+        tvd_terms<C>(py, y2, ym1, f0, yp1, dy, my);
+        C t = (sg * gc->nu[p][0]) * dx;
+        t = fmac(sg * gc->nu[p][1], dy, t);
+        t = fmac(gc->nk[p][0], mx, t);
+        t = fmac(gc->nk[p][1], my, t);
+        buf_st<S>(narrow<S, C>(hs[side] - t), out, so, po);
+      }
+    }
+  }
+}
+
 template <typename S>
 __global__ void __launch_bounds__(BLOCK)
 k_tvd(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
@@ -45,57 +111,41 @@ k_tvd(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
       const ProbParams<typename StepT2<S>::type>* __restrict__ pp) {
   using C = typename StepT2<S>::type;
   using L = D2Q36GH;
-  constexpr int Q = L::Q, P = L::P;
+  constexpr int Q = L::Q;
   constexpr uint32_t ss = sizeof(S);
   const uint32_t blk = xcd_block2(blockIdx.x, gridDim.x);
   const uint32_t wave0 = blk * BLOCK + (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u);
   const uint32_t s = __builtin_amdgcn_readfirstlane(fdiv(wave0, geo.div_ipad));
-  const uint32_t x = blk * BLOCK + threadIdx.x - s * geo.ipad;
-  if (s >= geo.nslices || x >= geo.inner) return;
+  if (s >= geo.nslices) return;
+  const int nx = int(geo.nx), ns = int(geo.nslices);
+  const int x0 = int(__builtin_amdgcn_readfirstlane(wave0 - s * geo.ipad));
+  if (x0 >= nx) return;                                // the row's padding slots
+  const int lane = int(threadIdx.x & 63u);
+  // lanes past the end of the row compute the cells of its start again
+  // (periodic) and store them into their own padding slots of the row
+  // (x0 + 64 <= ipad), which nothing reads: no lane's store is masked
+  const int xc = x0 + lane < nx ? x0 + lane : posmod(x0 + lane, nx);
+  int hx = xc;
+  if (lane == 0) hx = posmod(x0 - 1, nx);
+  if (lane == 1) hx = posmod(x0 - 2, nx);
+  if (lane == 62) hx = posmod(x0 + 65, nx);
+  if (lane == 63) hx = posmod(x0 + 64, nx);
+  const uint32_t xo = uint32_t(xc) * ss, hoff = uint32_t(hx) * ss, so = uint32_t(x0 + lane) * ss;
   const uint32_t bb = geo.sstride * ss, pb = geo.pstride * ss;
-  const int ns = int(geo.nslices), nx = int(geo.nx);
   Rsrc row[5];
 #pragma unroll
   for (int k = -2; k <= 2; ++k)
     row[k + 2] = block_rsrc(reinterpret_cast<const char*>(src) + size_t(wrapc(int(s) + k, ns)) * bb, bb);
-  uint32_t xo[5];
-#pragma unroll
-  for (int k = -2; k <= 2; ++k) xo[k + 2] = uint32_t(wrapc(int(x) + k, nx)) * ss;
 
-  // collision of the cell's own populations first (36 loads), then the flux
-  // differences velocity by velocity; scheduling barriers between groups of
-  // velocities keep the compiler from hoisting all 252 stencil loads at
-  // once (which would need far more than 128 VGPRs)
+  // level n of the cell stays in registers: the collision and the x
+  // neighbours of the advection are both taken from it
   C h[Q];
 #pragma unroll
-  for (int a = 0; a < Q; ++a) h[a] = widen<C, S>(buf_ld<S>(row[2], xo[2], uint32_t(a) * pb));
-  collide_gh<C>(h, gc, lc, pp);
+  for (int a = 0; a < Q; ++a) h[a] = widen<C, S>(buf_ld<S>(row[2], xo, uint32_t(a) * pb));
+  GHCollision<C> k;
+  collision_gh<C>(h, gc, lc, pp, k);
   const Rsrc out = block_rsrc(reinterpret_cast<char*>(dst) + size_t(s) * bb, bb);
-  constexpr int G = 4;   // velocities per group
-#pragma unroll
-  for (int a0 = 0; a0 < Q; a0 += G) {
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int a = a0; a < a0 + G && a < Q; ++a) {
-      const uint32_t po = uint32_t(a) * pb;
-      const int p = a % P;
-      const C sg = a < P ? C(1) : C(-1);
-      const bool px = gh_sign(a, 0) > 0, py = gh_sign(a, 1) > 0;
-      const C f0 = widen<C, S>(buf_ld<S>(row[2], xo[2], po));
-      const C xm1 = widen<C, S>(buf_ld<S>(row[2], xo[1], po));
-      const C xp1 = widen<C, S>(buf_ld<S>(row[2], xo[3], po));
-      const C x2 = widen<C, S>(buf_ld<S>(row[2], px ? xo[0] : xo[4], po));
-      const C ym1 = widen<C, S>(buf_ld<S>(row[1], xo[2], po));
-      const C yp1 = widen<C, S>(buf_ld<S>(row[3], xo[2], po));
-      const C y2 = widen<C, S>(buf_ld<S>(py ? row[0] : row[4], xo[2], po));
-      const C nux = sg * gc->nu[p][0], nuy = sg * gc->nu[p][1];
-      const C dx = px ? tvd_difference<C>(true, nux, x2, xm1, f0, xp1, C(0))
-                      : tvd_difference<C>(false, nux, C(0), xm1, f0, xp1, x2);
-      const C dy = py ? tvd_difference<C>(true, nuy, y2, ym1, f0, yp1, C(0))
-                      : tvd_difference<C>(false, nuy, C(0), ym1, f0, yp1, y2);
-      buf_st<S>(narrow<S, C>(h[a] - (dx + dy)), out, x * ss, po);
-    }
-  }
+  tvd_cell<S, C>(h, k, gc, row, xo, hoff, so, pb, out);
 }
 
 // h = rho S(T, u)/w (1 + amp xi) - 1 for cells [c0, c0 + count) (eq. feq0 at

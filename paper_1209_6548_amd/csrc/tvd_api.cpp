@@ -77,8 +77,11 @@ void pack_gh(const HostGH& gh, double nu_scale, GHConsts<C>& d) {
                                x * x * x * y, x * x * y * y, x * y * y * y, y * y * y * y};
     d.w[p] = C(gh.w[p]);
     for (int k = 0; k < GH_MONO; ++k) d.mono[p][k] = C(m[k]);
-    d.nu[p][0] = C(x * nu_scale);
-    d.nu[p][1] = C(y * nu_scale);
+    const double nx = x * nu_scale, ny = y * nu_scale;
+    d.nu[p][0] = C(nx);
+    d.nu[p][1] = C(ny);
+    d.nk[p][0] = C(0.5 * std::fabs(nx) * (1.0 - std::fabs(nx)));
+    d.nk[p][1] = C(0.5 * std::fabs(ny) * (1.0 - std::fabs(ny)));
   }
 }
 
