@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_traffic_poiseuille1024.json")
+TVD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tvd_traffic_periodic1024.json")
 
 
 def log(msg):
@@ -99,9 +100,12 @@ def bench_tvd(storage, steps, warmup):
     cells = nx * ny
     s = {"f64": 8, "f32": 4, "f16": 2}[storage]
     m = lat.read_moments()
+    traffic = measured_traffic(storage, TVD_TRAFFIC_FILE)
     out = dict(workload=TVD_CFG["name"], storage=storage, ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6,
                algorithmic_GBs=2 * 36 * s * cells / (ms * 1e-3) / 1e9, bytes_per_cell=2 * 36 * s,
-               kernel=f"k_tvd<{storage}>", finite=bool(np.isfinite(m["rho"]).all()))
+               kernel=f"k_tvd<{storage}>", traffic=traffic,
+               traffic_over_algorithmic=round(traffic / (2 * 36 * s * cells), 4) if traffic else None,
+               finite=bool(np.isfinite(m["rho"]).all()))
     lat.close()
     return out
 
@@ -177,13 +181,13 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def measured_traffic(storage):
-    """HBM bytes per step launch on the headline workload from the FETCH_SIZE /
-    WRITE_SIZE counters (calibrated against a copy of known size), or None if
-    the step kernel's sources changed since they were taken."""
+def measured_traffic(storage, path=TRAFFIC_FILE):
+    """HBM bytes per launch of a kernel on its 1024 x 1024 workload from the
+    FETCH_SIZE / WRITE_SIZE counters (calibrated against a copy of known
+    size), or None if the kernel's sources changed since they were taken."""
     import hashlib
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
         h = hashlib.sha256()
         for f in rec["sources"]:

@@ -90,12 +90,13 @@ __device__ __forceinline__ void raw_moments_gh(const C (&h)[D2Q36GH::Q], const G
     }
   }
   m.S2[1][0] = m.S2[0][1];
-  if (third) {
-    m.S3[0][0][0] = s111;
-    m.S3[0][0][1] = m.S3[0][1][0] = m.S3[1][0][0] = s112;
-    m.S3[0][1][1] = m.S3[1][0][1] = m.S3[1][1][0] = s122;
-    m.S3[1][1][1] = s222;
-  }
+  // written on both paths (zero without `third`): a store under the
+  // condition alone leaves the compiler a store through a selected pointer,
+  // which keeps these fields in scratch memory
+  m.S3[0][0][0] = s111;
+  m.S3[0][0][1] = m.S3[0][1][0] = m.S3[1][0][0] = s112;
+  m.S3[0][1][1] = m.S3[1][0][1] = m.S3[1][1][0] = s122;
+  m.S3[1][1][1] = s222;
 }
 
 // Forward-Euler collision and force of the scheme (Sec. 3.1):

@@ -67,10 +67,13 @@ __device__ __forceinline__ void tvd_cell(const C (&h)[D2Q36GH::Q], const GHColli
                                          uint32_t hoff, uint32_t so, uint32_t pb, const Rsrc out) {
   using L = D2Q36GH;
   constexpr int P = L::P;
-  constexpr int G = 2;   // velocity pairs per scheduling group
+  constexpr int G = 3;   // velocity pairs per scheduling group
 #pragma unroll
   for (int p0 = 0; p0 < P; p0 += G) {
     __builtin_amdgcn_sched_barrier(0);
+    // the plane offsets a pb are formed in each group rather than all at
+    // once up front (36 of them would spill out of the scalar registers)
+    asm volatile("" : "+s"(pb));
 #pragma unroll
     for (int p = p0; p < p0 + G && p < P; ++p) {
       C hs[2];
@@ -125,11 +128,11 @@ k_tvd(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
   // (periodic) and store them into their own padding slots of the row
   // (x0 + 64 <= ipad), which nothing reads: no lane's store is masked
   const int xc = x0 + lane < nx ? x0 + lane : posmod(x0 + lane, nx);
-  int hx = xc;
-  if (lane == 0) hx = posmod(x0 - 1, nx);
+  // the other lanes of the halo load repeat an address of lanes 0 or 63, so
+  // that it touches only the lines beside the wavefront's own
+  int hx = lane < 32 ? posmod(x0 - 1, nx) : posmod(x0 + 64, nx);
   if (lane == 1) hx = posmod(x0 - 2, nx);
   if (lane == 62) hx = posmod(x0 + 65, nx);
-  if (lane == 63) hx = posmod(x0 + 64, nx);
   const uint32_t xo = uint32_t(xc) * ss, hoff = uint32_t(hx) * ss, so = uint32_t(x0 + lane) * ss;
   const uint32_t bb = geo.sstride * ss, pb = geo.pstride * ss;
   Rsrc row[5];
