@@ -27,13 +27,30 @@ Where the denominator of Theta vanishes the limited term (f_{i+1} - f_i) Psi
 is zero whatever Psi is; it is taken as zero. Every right-hand-side term is
 evaluated at level n. The collision and force terms are those of the
 on-lattice oracle with the Euler weights (omega = dt/tau, phi = 1), built
-from the moments of f^n. Boundaries: periodic in every axis.
+from the moments of f^n.
+
+Boundaries: periodic in every axis, or (walls=True) diffuse walls across
+the last axis after Sec. 3.2 (the first version of the boundary conditions
+of Sofonea et al. that the paper adopts). The first and last nodes of that
+axis lie on the walls and are updated like every node; the two ghost nodes
+beyond each wall that the stencil reaches hold copies of the wall node.
+After the update, the wall node's populations that move into the gas
+(c.n > 0, n the inward normal) are replaced by rho_W S(T_W, u_W), with
+rho_W = sum_{c.n<0} |c.n| f / sum_{c.n>0} |c.n| S over the populations of
+the first node off the wall (the superscripts 0 and 1 of the paper's
+formula are node rows along the normal, as j in f^{n,j}): the wall emits
+the normal particle flux that reaches it from that node. The scheme does
+not conserve mass exactly: where the flow near the wall is not uniform
+the emitted flux differs from what crosses the wall face, by a small
+amount per step. Walls are fully diffuse (the paper implements only
+gamma = 1) at a fixed temperature.
 
 Time step: dt = CFL dx / max|c|, CFL in (0, 1] (the TVD update is stable for
-|nu| <= 1); dx = 1/N_L.
+|nu| <= 1); dx = 1/N_L, N_L = nx for periodic boxes and the wall distance
+ny - 1 in nodes for channels.
 """
 
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 from itertools import product
 
 import numpy as np
@@ -79,7 +96,8 @@ class ProductSet:
 
 @dataclass
 class TVDProblem:
-    """A periodic lattice for the paper's scheme. dims = (nx, ny)."""
+    """A lattice for the paper's scheme. dims = (nx, ny); walls=True puts
+    diffuse walls on the first and last node rows of the last axis."""
     vs: object
     dims: tuple
     Kn: float
@@ -88,6 +106,9 @@ class TVDProblem:
     g: tuple = (0.0, 0.0, 0.0)
     cfl: float = 0.5
     n_ref: int = 0
+    walls: bool = False
+    wall_lo: lattice.Wall = field(default_factory=lattice.Wall)
+    wall_hi: lattice.Wall = field(default_factory=lattice.Wall)
 
     def __post_init__(self):
         self.D = self.vs.D
@@ -96,8 +117,14 @@ class TVDProblem:
             raise ValueError("dims must have one extent per dimension")
         if not 0.0 < self.cfl <= 1.0:
             raise ValueError("the TVD update needs 0 < CFL <= 1")
+        if self.walls:
+            if self.dims[-1] < 3:
+                raise ValueError("a channel needs two wall nodes and at least one node between them")
+            for w in (self.wall_lo, self.wall_hi):
+                if w.gamma != 1.0 or w.heat_amp != 0.0:
+                    raise ValueError("the scheme's walls are fully diffuse at a fixed temperature")
         if self.n_ref == 0:
-            self.n_ref = self.dims[0]
+            self.n_ref = self.dims[-1] - 1 if self.walls else self.dims[0]
         self.dx = 1.0 / self.n_ref
         self.dt = self.cfl * self.dx / np.abs(self.vs.c).max()
         self.hs = 0.0                      # forward Euler: no change of variable
@@ -105,7 +132,6 @@ class TVDProblem:
         self.b = model.b_from_prandtl(self.Pr)
         self.gvec = np.asarray(self.g[: self.D], dtype=np.float64)
         self.M = int(np.prod(self.dims))
-        self.walls = False
 
     def grid(self, f):
         """View a (Q, M) state as (Q, *reversed dims): axis -1 is x."""
@@ -127,8 +153,8 @@ def _limited(num, den):
 
 def face_flux(f, nu, axis):
     """Upwind TVD flux F_{i+1/2} at the face between cell i and i + 1 along
-    the grid axis `axis` for one velocity (f an array over cells, periodic);
-    nu = c dt / dx of that velocity along the axis."""
+    the grid axis `axis` for one velocity (f an array over cells, periodic
+    within the array); nu = c dt / dx of that velocity along the axis."""
     fm1 = np.roll(f, 1, axis)        # f_{i-1}
     fp1 = np.roll(f, -1, axis)       # f_{i+1}
     fp2 = np.roll(f, -2, axis)       # f_{i+2}
@@ -136,6 +162,22 @@ def face_flux(f, nu, axis):
     if nu > 0:
         return f + 0.5 * (1.0 - nu) * _limited(f - fm1, d)
     return fp1 - 0.5 * (1.0 - abs(nu)) * _limited(fp2 - fp1, d)
+
+
+def flux_difference(f, nu, axis, walls):
+    """nu [F_{i+1/2} - F_{i-1/2}] along one grid axis for one velocity. The
+    axis is extended by two nodes on each side: periodic images, or (walls)
+    ghost nodes that copy the wall node. The fluxes are taken on the
+    extended array, whose own wrap-around never reaches a kept value."""
+    n = f.shape[axis]
+    pad = [(0, 0)] * f.ndim
+    pad[axis] = (2, 2)
+    ext = np.pad(f, pad, mode="edge" if walls else "wrap")
+    Fr = face_flux(ext, nu, axis)                # F at the right face of every extended node
+    keep = np.arange(2, n + 2)
+    right = np.take(Fr, keep, axis=axis)         # F_{i+1/2}
+    left = np.take(Fr, keep - 1, axis=axis)      # F_{i-1/2} = F_{(i-1)+1/2}
+    return nu * (right - left)
 
 
 def advection(f, prob):
@@ -149,15 +191,41 @@ def advection(f, prob):
             if nu == 0.0:
                 continue
             axis = prob.D - 1 - d    # grid axis of coordinate d (x is last)
-            Fr = face_flux(g[a], nu, axis)
-            Fl = np.roll(Fr, 1, axis)
-            out[a] += nu * (Fr - Fl)
+            walls = prob.walls and d == prob.D - 1
+            out[a] += flux_difference(g[a], nu, axis, walls)
     return out.reshape(f.shape)
 
 
+def wall_state(prob, side):
+    """S_alpha(T_W, u_W) (eq. feq0 at order N, rho = 1) of wall `side` and
+    c.n with n its inward normal."""
+    w = prob.wall_lo if side == 0 else prob.wall_hi
+    u = np.asarray(w.u[: prob.D], dtype=np.float64)
+    S = model.truncated_maxwellian(np.ones(1), u[None, :], np.full(1, w.T), prob.vs.c, prob.vs.w, prob.N)[:, 0]
+    cn = prob.vs.c[:, -1] * (1.0 if side == 0 else -1.0)
+    return S, cn
+
+
+def wall_emission(f, prob):
+    """Sec. 3.2: the wall nodes' populations with c.n > 0 become rho_W S,
+    rho_W from the flux toward the wall at the first node off it."""
+    g = prob.grid(f).copy()
+    n = prob.dims[-1]
+    for side, (jw, ji) in enumerate(((0, 1), (n - 1, n - 2))):
+        S, cn = wall_state(prob, side)
+        inc, out = cn < 0, cn > 0
+        wall = g[:, jw]
+        inner = g[:, ji]
+        rho_w = np.tensordot(np.abs(cn[inc]), inner[inc], axes=1) / np.dot(np.abs(cn[out]), S[out])
+        wall[out] = S[out].reshape((-1,) + (1,) * (wall.ndim - 1)) * rho_w[None]
+    return g.reshape(f.shape)
+
+
 def step(f, prob):
-    """One step of the paper's scheme: every term at level n."""
-    return lattice.collide(f, prob) - advection(f, prob)
+    """One step of the paper's scheme: every term at level n, then the wall
+    emission of Sec. 3.2 (walls=True)."""
+    f1 = lattice.collide(f, prob) - advection(f, prob)
+    return wall_emission(f1, prob) if prob.walls else f1
 
 
 def run(f, prob, nsteps):
