@@ -260,12 +260,20 @@ const char* esbgk_batch_last_error(const esbgk_batch* b);
  * its mirror image (upwind cell i + 1) for c < 0. Every term is evaluated at
  * level n; one fused kernel launch per step. The stored state is the
  * physical f (deviational h = f/w - 1 in the storage type, in the velocity
- * order of esbgk_tvd_info). Boundaries: periodic in x and y.
+ * order of esbgk_tvd_info).
  *
- * Shape: velset = ESBGK_D2Q36GH, nz = 1, walls = 0, scheme = ESBGK_EULER,
- * storage F64 / F32 / F16 (FP32 compute for the last two), n_ref = N_L
- * (0: nx). The time step is dt = cfl dx / max|c| with dx = 1/N_L and
- * 0 < cfl <= 1. */
+ * Boundaries: periodic in x; in y periodic (walls = 0) or bounded by the
+ * diffuse walls of Sec. 3.2 (walls = 1): rows 0 and ny - 1 lie on the
+ * walls and are updated like every row, the ghost rows the stencil reaches
+ * beyond a wall copy the wall row, and after each step the wall row's
+ * populations moving into the gas become rho_W S(T_W, u_W) with rho_W the
+ * normal flux toward the wall at the first row off it over that of S (a
+ * second small kernel launch). Walls are fully diffuse at fixed T_W, u_W.
+ *
+ * Shape: velset = ESBGK_D2Q36GH, nz = 1, walls = 0 or 1 (ny >= 3),
+ * scheme = ESBGK_EULER, storage F64 / F32 / F16 (FP32 compute for the last
+ * two), n_ref = N_L (0: nx, or the wall distance ny - 1 with walls). The
+ * time step is dt = cfl dx / max|c| with dx = 1/N_L and 0 < cfl <= 1. */
 typedef struct esbgk_tvd esbgk_tvd;
 
 /* Abscissae c[36][2] and weights w[36] of ESBGK_D2Q36GH (either may be
@@ -285,6 +293,10 @@ double esbgk_tvd_time_step(const esbgk_tvd* t);
 /* Gas (as esbgk_set_gas); E_UNSTABLE when forward Euler is unstable at
  * rho = T = 1 (dt/tau >= 2 or dt/(Pr tau) >= 2). */
 int esbgk_tvd_set_gas(esbgk_tvd* t, double Kn, double Pr, double varpi);
+/* Wall side (0: y = 0, 1: y = ny - 1) at temperature T_w > 0 moving with
+ * u_w = (u_x, 0, 0) (NULL: at rest); defaults T_w = 1, at rest. E_INVALID
+ * on a lattice without walls. */
+int esbgk_tvd_set_wall(esbgk_tvd* t, int side, double T_w, const double u_w[3]);
 int esbgk_tvd_set_body_force(esbgk_tvd* t, const double g[3]);
 /* Initial state f = rho S(T, u) (1 + amplitude noise) as
  * esbgk_init_equilibrium (u is [2][cells], noise [36][cells]). */

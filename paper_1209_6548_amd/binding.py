@@ -104,6 +104,7 @@ def lib():
             "esbgk_tvd_time_step": (D, [P]),
             "esbgk_tvd_set_gas": (I, [P, D, D, D]),
             "esbgk_tvd_set_body_force": (I, [P, DP]),
+            "esbgk_tvd_set_wall": (I, [P, I, D, DP]),
             "esbgk_tvd_init_equilibrium": (I, [P, DP, DP, DP, DP, D]),
             "esbgk_tvd_set_populations": (I, [P, DP]),
             "esbgk_tvd_get_populations": (I, [P, DP]),
@@ -402,17 +403,19 @@ def tvd_velocity_set():
 
 class TVDLattice:
     """The paper's own scheme (forward Euler, TVD minmod fluxes) on the
-    6-point Gauss-Hermite product set D2Q36, periodic in x and y."""
+    6-point Gauss-Hermite product set D2Q36: periodic in x, and in y
+    periodic or (walls=True) bounded by diffuse walls on rows 0 and ny - 1."""
 
     Q, D, N = 36, 2, 4
 
-    def __init__(self, nx=64, ny=64, storage="f32", cfl=0.5, n_ref=0, device="cuda:0"):
+    def __init__(self, nx=64, ny=64, storage="f32", cfl=0.5, n_ref=0, walls=False, device="cuda:0"):
         import torch
         self.device = torch.device(device)
         self.dims = (nx, ny)
         self.cells = nx * ny
         self.storage = storage
-        self.shape = Shape(D2Q36GH, nx, ny, 1, 0, _STORAGE[storage], EULER, n_ref)
+        self.walls = bool(walls)
+        self.shape = Shape(D2Q36GH, nx, ny, 1, int(self.walls), _STORAGE[storage], EULER, n_ref)
         L = lib()
         nbytes = L.esbgk_tvd_workspace_bytes(ctypes.byref(self.shape))
         if nbytes == 0:
@@ -457,6 +460,11 @@ class TVDLattice:
         gg = np.zeros(3)
         gg[:len(g)] = g
         self._check(lib().esbgk_tvd_set_body_force(self._t, _dp(gg)), "tvd_set_body_force")
+
+    def set_wall(self, side, T, u=(0.0, 0.0, 0.0)):
+        uu = np.zeros(3)
+        uu[:len(u)] = u
+        self._check(lib().esbgk_tvd_set_wall(self._t, int(side), float(T), _dp(uu)), "tvd_set_wall")
 
     def init_equilibrium(self, rho=None, u=None, T=None, noise=None, amplitude=0.0):
         rho = _f64(rho, (self.cells,))

@@ -328,24 +328,29 @@ const HostGH* host_gh() {
   return ok ? &gh : nullptr;
 }
 
-// S(T, u)(c_alpha) / w_alpha - 1: eq. feq0 with rho = 1, truncated at order N.
-double shat_minus_one(const HostLattice& lat, int a, double T, const double u[3]) {
-  const int D = lat.D;
+// S(T, u)(c) / w - 1 at the velocity c[D]: eq. feq0 with rho = 1, truncated
+// at order N.
+double shat_minus_one_at(int D, int N, const double* c, double T, const double u[3]) {
   double cu = 0, uu = 0, cc = 0;
   for (int i = 0; i < D; ++i) {
-    const double ci = lat.r * lat.e[size_t(a) * 3 + i];
-    cu += ci * u[i];
+    cu += c[i] * u[i];
     uu += u[i] * u[i];
-    cc += ci * ci;
+    cc += c[i] * c[i];
   }
   const double th = T - 1.0;
   double s = cu + 0.5 * (cu * cu - uu + th * (cc - D)) + cu / 6.0 * (cu * cu - 3.0 * uu + 3.0 * th * (cc - D - 2));
-  if (lat.N >= 4) {
+  if (N >= 4) {
     s += (cu * cu * cu * cu - 6.0 * cu * cu * uu + 3.0 * uu * uu) / 24.0 +
          th / 4.0 * ((cc - D - 2) * (cu * cu - uu) - 2.0 * cu * cu) +
          th * th / 8.0 * (cc * cc - 2.0 * (D + 2) * cc + D * (D + 2));
   }
   return s;
+}
+
+double shat_minus_one(const HostLattice& lat, int a, double T, const double u[3]) {
+  double c[3];
+  for (int i = 0; i < lat.D; ++i) c[i] = lat.r * lat.e[size_t(a) * 3 + i];
+  return shat_minus_one_at(lat.D, lat.N, c, T, u);
 }
 
 HostProblem make_problem(const HostLattice& lat, int n_ref, int scheme, double Kn, double Pr, double varpi,

@@ -32,6 +32,8 @@ const HostGH* host_gh();
 
 // S(T, u)/w - 1 at velocity a (eq. feq0, rho = 1, order N of the lattice).
 double shat_minus_one(const HostLattice& lat, int a, double T, const double u[3]);
+// The same at an arbitrary velocity c[D], truncated at order N.
+double shat_minus_one_at(int D, int N, const double* c, double T, const double u[3]);
 
 // FP64 version of ProbParams.
 struct HostProblem {

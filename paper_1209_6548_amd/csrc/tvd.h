@@ -23,7 +23,24 @@ struct TVDArgs {
   hipStream_t stream;
 };
 
+// Diffuse walls of the TVD scheme (Sec. 3.2) on the first (side 0, inward
+// normal +y) and last (side 1, normal -y) node rows:
+//   kin[s][a]  |c.n| w_a / sum_{c.n>0} |c.n| S_a for the velocities moving
+//              toward wall s (c.n < 0), 0 for the others
+//   k0[s]      the sum of kin[s][.], so that rho_W = k0 + sum_a kin h_a
+//              over the first node off the wall
+//   sw[s][a]   S_a(T_W, u_W) / w_a for the velocities moving into the gas
+//              (the wall node's new h_a is rho_W sw - 1), 0 for the others
+template <typename C>
+struct TVDWalls {
+  C kin[2][36];
+  C k0[2];
+  C sw[2][36];
+};
+
 hipError_t launch_tvd_step(int storage, const TVDArgs& a);
+// Re-emission at both walls into a.dst (the level just written by the step).
+hipError_t launch_tvd_walls(int storage, const TVDArgs& a, const void* walls);
 hipError_t launch_tvd_init(int storage, const TVDArgs& a, const double* c, const double* rho, const double* u,
                            const double* T, const double* noise, double amp, uint32_t c0, uint32_t count);
 hipError_t launch_tvd_moments(int storage, const TVDArgs& a, uint32_t c0, uint32_t count, double* out);

@@ -4,9 +4,11 @@
 // stencil of the stored level and the forward-Euler ES-BGK collision and
 // force from the cell's own populations, and writes
 //   h^{n+1} = h^n - omega (h^n - h_ES) + dt F/w - nu_x [...] - nu_y [...].
-// Periodic in both axes. Populations use the slice layout of Geometry (slice
-// = row y); a wavefront shares its row, so the rows y-2..y+2 are scalar
-// buffer resources and only the x offsets are per lane.
+// Periodic in x; in y periodic or bounded by the diffuse walls of Sec. 3.2
+// (ghost rows copy the wall row; a second small kernel re-emits at the
+// walls after each step). Populations use the slice layout of Geometry
+// (slice = row y); a wavefront shares its row, so the rows y-2..y+2 are
+// scalar buffer resources and only the x offsets are per lane.
 
 #include <hip/hip_runtime.h>
 
@@ -135,10 +137,14 @@ k_tvd(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
   if (lane == 62) hx = posmod(x0 + 65, nx);
   const uint32_t xo = uint32_t(xc) * ss, hoff = uint32_t(hx) * ss, so = uint32_t(x0 + lane) * ss;
   const uint32_t bb = geo.sstride * ss, pb = geo.pstride * ss;
+  // rows y-2..y+2: periodic images, or (walls) ghost rows that copy the
+  // wall row (Sec. 3.2)
   Rsrc row[5];
 #pragma unroll
-  for (int k = -2; k <= 2; ++k)
-    row[k + 2] = block_rsrc(reinterpret_cast<const char*>(src) + size_t(wrapc(int(s) + k, ns)) * bb, bb);
+  for (int k = -2; k <= 2; ++k) {
+    const int r = geo.walls ? min(max(int(s) + k, 0), ns - 1) : wrapc(int(s) + k, ns);
+    row[k + 2] = block_rsrc(reinterpret_cast<const char*>(src) + size_t(r) * bb, bb);
+  }
 
   // level n of the cell stays in registers: the collision and the x
   // neighbours of the advection are both taken from it
@@ -149,6 +155,32 @@ k_tvd(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
   collision_gh<C>(h, gc, lc, pp, k);
   const Rsrc out = block_rsrc(reinterpret_cast<char*>(dst) + size_t(s) * bb, bb);
   tvd_cell<S, C>(h, k, gc, row, xo, hoff, so, pb, out);
+}
+
+// Re-emission at the walls (Sec. 3.2) after a step: for column x of wall
+// side = blockIdx.y, rho_W from the populations moving toward the wall at
+// the first node off it, then h = rho_W S/w - 1 for the wall node's
+// populations moving into the gas.
+template <typename S>
+__global__ void __launch_bounds__(BLOCK)
+k_tvd_walls(Geometry geo, S* __restrict__ pop, const TVDWalls<typename StepT2<S>::type>* __restrict__ w) {
+  using C = typename StepT2<S>::type;
+  const uint32_t x = blockIdx.x * BLOCK + threadIdx.x;
+  const int side = int(blockIdx.y);
+  if (x >= geo.inner) return;
+  const uint32_t jw = side ? geo.nslices - 1 : 0, ji = side ? geo.nslices - 2 : 1;
+  const size_t ew = size_t(jw) * geo.sstride + x, ei = size_t(ji) * geo.sstride + x;
+  C rho = w->k0[side];
+#pragma unroll
+  for (int a = 0; a < D2Q36GH::Q; ++a) {
+    const bool toward = side == 0 ? gh_sign(a, 1) < 0 : gh_sign(a, 1) > 0;
+    if (toward) rho = fmac(w->kin[side][a], widen<C, S>(pop[size_t(a) * geo.pstride + ei]), rho);
+  }
+#pragma unroll
+  for (int a = 0; a < D2Q36GH::Q; ++a) {
+    const bool into_gas = side == 0 ? gh_sign(a, 1) > 0 : gh_sign(a, 1) < 0;
+    if (into_gas) pop[size_t(a) * geo.pstride + ew] = narrow<S, C>(rho * w->sw[side][a] - C(1));
+  }
 }
 
 // h = rho S(T, u)/w (1 + amp xi) - 1 for cells [c0, c0 + count) (eq. feq0 at
@@ -235,7 +267,20 @@ static hipError_t tvd_moments_t(const TVDArgs& a, uint32_t c0, uint32_t count, d
   return hipGetLastError();
 }
 
+template <typename S>
+static hipError_t tvd_walls_t(const TVDArgs& a, const void* walls) {
+  using C = typename StepT2<S>::type;
+  const dim3 grid((a.geo.inner + BLOCK - 1) / BLOCK, 2);
+  hipLaunchKernelGGL(k_tvd_walls<S>, grid, dim3(BLOCK), 0, a.stream, a.geo, static_cast<S*>(a.dst),
+                     static_cast<const TVDWalls<C>*>(walls));
+  return hipGetLastError();
+}
+
 hipError_t launch_tvd_step(int storage, const TVDArgs& a) { ESBGK_TVD_DISPATCH(storage, tvd_step_t<S>(a)); }
+
+hipError_t launch_tvd_walls(int storage, const TVDArgs& a, const void* walls) {
+  ESBGK_TVD_DISPATCH(storage, (tvd_walls_t<S>(a, walls)));
+}
 
 hipError_t launch_tvd_init(int storage, const TVDArgs& a, const double* c, const double* rho, const double* u,
                            const double* T, const double* noise, double amp, uint32_t c0, uint32_t count) {

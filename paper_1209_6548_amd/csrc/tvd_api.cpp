@@ -27,7 +27,7 @@ size_t ssize(int storage) { return storage == ESBGK_F64 ? 8 : (storage == ESBGK_
 size_t csize(int storage) { return storage == ESBGK_F64 ? 8 : 4; }
 
 struct TLayout {
-  size_t pop[2], gc, lc, pp, gc64, lc64, pp64, c, staging, total;
+  size_t pop[2], gc, lc, pp, gc64, lc64, pp64, walls, c, staging, total;
 };
 
 bool valid_tvd_shape(const esbgk_shape* s, Geometry* g, std::string* why) {
@@ -35,13 +35,15 @@ bool valid_tvd_shape(const esbgk_shape* s, Geometry* g, std::string* why) {
   if (!s) return fail("null shape");
   if (s->velset != ESBGK_D2Q36GH) return fail("velset must be ESBGK_D2Q36GH");
   if (s->nx < 1 || s->ny < 1 || s->nz != 1) return fail("extents: nx, ny >= 1 and nz = 1");
-  if (s->walls != 0) return fail("the TVD scheme is periodic (walls = 0)");
+  if (s->walls != 0 && s->walls != 1) return fail("walls must be 0 (periodic) or 1 (walls across y)");
+  if (s->walls && s->ny < 3) return fail("a channel needs ny >= 3 (two wall rows and one between)");
   if (s->storage < ESBGK_F64 || s->storage > ESBGK_F16) return fail("storage must be F64, F32 or F16");
   if (s->scheme != ESBGK_EULER) return fail("the paper's scheme is forward Euler (scheme = ESBGK_EULER)");
   if (s->n_ref < 0) return fail("n_ref must be >= 0");
   if (!host_gh()) return fail("velocity set tables unavailable");
   Geometry tmp;
-  if (!make_geometry(2, QGH, uint32_t(s->nx), uint32_t(s->ny), 1, false, true, ssize(s->storage), g ? *g : tmp))
+  if (!make_geometry(2, QGH, uint32_t(s->nx), uint32_t(s->ny), 1, s->walls != 0, true, ssize(s->storage),
+                     g ? *g : tmp))
     return fail("lattice too large for the slice layout (one row of populations must be < 4 GiB)");
   return true;
 }
@@ -60,6 +62,7 @@ TLayout tlayout(const esbgk_shape* s, const Geometry& g) {
   L.gc64 = cs == 8 ? L.gc : take(sizeof(GHConsts<double>));
   L.lc64 = cs == 8 ? L.lc : take(sizeof(LatConsts<double>));
   L.pp64 = cs == 8 ? L.pp : take(sizeof(ProbParams<double>));
+  L.walls = take(cs == 8 ? sizeof(TVDWalls<double>) : sizeof(TVDWalls<float>));
   L.c = take(sizeof(double) * QGH * 2);
   const size_t stage = std::min<size_t>(cells, STAGE_CELLS);
   L.staging = take(stage * size_t(std::max(NFIELDS, 4 + QGH)) * sizeof(double));
@@ -85,6 +88,33 @@ void pack_gh(const HostGH& gh, double nu_scale, GHConsts<C>& d) {
   }
 }
 
+// Wall tables of Sec. 3.2 (see TVDWalls) from the walls' T and u.
+template <typename C>
+void pack_walls(const HostGH& gh, const double Tw[2], const double uw[2][3], TVDWalls<C>& d) {
+  std::memset(&d, 0, sizeof(d));
+  for (int side = 0; side < 2; ++side) {
+    const double nrm = side == 0 ? 1.0 : -1.0;   // inward normal along y
+    double den = 0.0, sw[QGH];
+    for (int a = 0; a < QGH; ++a) {
+      sw[a] = 1.0 + shat_minus_one_at(2, 4, gh.c[a], Tw[side], uw[side]);
+      const double cn = nrm * gh.c[a][1];
+      if (cn > 0) den += cn * gh.w[a] * sw[a];
+    }
+    double k0 = 0.0;
+    for (int a = 0; a < QGH; ++a) {
+      const double cn = nrm * gh.c[a][1];
+      if (cn < 0) {
+        const double k = -cn * gh.w[a] / den;
+        d.kin[side][a] = C(k);
+        k0 += k;
+      } else {
+        d.sw[side][a] = C(sw[a]);
+      }
+    }
+    d.k0[side] = C(k0);
+  }
+}
+
 }  // namespace
 
 struct esbgk_tvd {
@@ -100,6 +130,8 @@ struct esbgk_tvd {
   std::string err;
   double Kn = 0.1, Pr = 1.0, varpi = 0.5, cfl = 0.5, dt = 0.0, dx = 0.0;
   double g[3] = {0, 0, 0};
+  double Tw[2] = {1.0, 1.0};
+  double uw[2][3] = {{0, 0, 0}, {0, 0, 0}};
   char* at(size_t off) const { return ws + off; }
   bool f64() const { return shape.storage == ESBGK_F64; }
 };
@@ -188,6 +220,17 @@ int upload_tvd(esbgk_tvd* c) {
     TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.gc), &g32, sizeof(g32), hipMemcpyHostToDevice, c->stream), "upload");
     TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.lc), &l32, sizeof(l32), hipMemcpyHostToDevice, c->stream), "upload");
   }
+  if (c->shape.walls) {
+    static thread_local TVDWalls<double> w64;
+    static thread_local TVDWalls<float> w32;
+    if (c->f64()) {
+      pack_walls<double>(gh, c->Tw, c->uw, w64);
+      TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.walls), &w64, sizeof(w64), hipMemcpyHostToDevice, c->stream), "upload");
+    } else {
+      pack_walls<float>(gh, c->Tw, c->uw, w32);
+      TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.walls), &w32, sizeof(w32), hipMemcpyHostToDevice, c->stream), "upload");
+    }
+  }
   TVD_HIP(c, hipStreamSynchronize(c->stream), "upload");
   return ESBGK_OK;
 }
@@ -268,7 +311,7 @@ int esbgk_tvd_create(const esbgk_shape* shape, double cfl, void* d_workspace, si
   c->ws = static_cast<char*>(d_workspace);
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->cfl = cfl;
-  const int n_ref = shape->n_ref > 0 ? shape->n_ref : shape->nx;
+  const int n_ref = shape->n_ref > 0 ? shape->n_ref : (shape->walls ? shape->ny - 1 : shape->nx);
   c->dx = 1.0 / double(n_ref);
   const HostGH& gh = *host_gh();
   c->dt = cfl * c->dx / gh.xi[2];
@@ -312,6 +355,23 @@ int esbgk_tvd_set_gas(esbgk_tvd* c, double Kn, double Pr, double varpi) {
   c->Kn = Kn;
   c->Pr = Pr;
   c->varpi = varpi;
+  return upload_tvd(c);
+}
+
+int esbgk_tvd_set_wall(esbgk_tvd* c, int side, double T_w, const double u_w[3]) {
+  TVD_CHECK(c);
+  if (!c->shape.walls) return tset_err(c, ESBGK_E_INVALID, "the lattice has no walls");
+  if (side != 0 && side != 1) return tset_err(c, ESBGK_E_INVALID, "side must be 0 or 1");
+  if (!(T_w > 0.0) || !std::isfinite(T_w)) return tset_err(c, ESBGK_E_INVALID, "T_w must be > 0");
+  double u[3] = {0, 0, 0};
+  if (u_w)
+    for (int i = 0; i < 3; ++i) {
+      if (!std::isfinite(u_w[i])) return tset_err(c, ESBGK_E_INVALID, "u_w must be finite");
+      u[i] = i < 2 ? u_w[i] : 0.0;
+    }
+  if (u[1] != 0.0) return tset_err(c, ESBGK_E_INVALID, "a wall moves in its own plane (u_w[1] = 0)");
+  c->Tw[side] = T_w;
+  for (int i = 0; i < 3; ++i) c->uw[side][i] = u[i];
   return upload_tvd(c);
 }
 
@@ -405,7 +465,9 @@ int esbgk_tvd_step(esbgk_tvd* c, int64_t n) {
   if (n < 0) return tset_err(c, ESBGK_E_INVALID, "n must be >= 0");
   if (!c->state_set) return tset_err(c, ESBGK_E_STATE, "no state set");
   for (int64_t k = 0; k < n; ++k) {
-    TVD_HIP(c, launch_tvd_step(c->shape.storage, targs(c)), "step");
+    const TVDArgs a = targs(c);
+    TVD_HIP(c, launch_tvd_step(c->shape.storage, a), "step");
+    if (c->shape.walls) TVD_HIP(c, launch_tvd_walls(c->shape.storage, a, c->at(c->lay.walls)), "walls");
     c->cur ^= 1;
     c->steps += 1;
   }

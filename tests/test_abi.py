@@ -109,12 +109,16 @@ def test_tvd_workspace_bytes_validates_shapes():
     assert lib.esbgk_tvd_workspace_bytes(ctypes.byref(ok)) >= 2 * 36 * 64 * 32 * 4
     bad = [B.Shape(B.D2Q37, 8, 8, 1, 0, B.F32, B.EULER, 0),    # on-lattice set
            B.Shape(B.D2Q36GH, 8, 8, 2, 0, B.F32, B.EULER, 0),  # 3-D
-           B.Shape(B.D2Q36GH, 8, 8, 1, 1, B.F32, B.EULER, 0),  # walls
+           B.Shape(B.D2Q36GH, 8, 2, 1, 1, B.F32, B.EULER, 0),  # walls need ny >= 3
+           B.Shape(B.D2Q36GH, 8, 8, 1, 2, B.F32, B.EULER, 0),  # walls flag
            B.Shape(B.D2Q36GH, 8, 8, 1, 0, B.F32, B.TRAPEZOID, 0),
            B.Shape(B.D2Q36GH, 0, 8, 1, 0, B.F32, B.EULER, 0),
            B.Shape(B.D2Q36GH, 8, 8, 1, 0, 3, B.EULER, 0)]
     for s in bad:
         assert lib.esbgk_tvd_workspace_bytes(ctypes.byref(s)) == 0
+    # a channel (walls across y) needs two wall rows and one between
+    ch = B.Shape(B.D2Q36GH, 8, 3, 1, 1, B.F64, B.EULER, 0)
+    assert lib.esbgk_tvd_workspace_bytes(ctypes.byref(ch)) > 0
     # and the on-lattice entry points reject the off-lattice set
     assert lib.esbgk_workspace_bytes(ctypes.byref(ok)) == 0
 

@@ -13,6 +13,7 @@ rounding-sized amount only.
 import numpy as np
 import pytest
 
+from oracle import lattice as OL
 from oracle import offlattice as OF
 from tests import helpers as H
 
@@ -31,16 +32,29 @@ def _fields(f, prob):
             "sigma": np.array([sigma[:, 0, 0], sigma[:, 0, 1], sigma[:, 1, 1]]), "q": q.T.copy()}
 
 
-def _pair(dims, storage, cfl=0.5, Kn=0.005, Pr=2 / 3, g=(0.02, -0.01), seed=5, amp=0.02):
+WALLS = dict(T=(0.98, 1.04), u=(-0.04, 0.05))
+
+
+def _pair(dims, storage, cfl=0.5, Kn=0.005, Pr=2 / 3, g=(0.02, -0.01), seed=5, amp=0.02, walls=None):
+    """GPU lattice and oracle problem with the same seeded start; walls =
+    dict(T=(T_lo, T_hi), u=(u_lo, u_hi)) puts diffuse walls on the first
+    and last rows."""
     from paper_1209_6548_amd import TVDLattice
     # N_L is the longer extent, so that dt = CFL dx / max|c| keeps the
     # forward-Euler collision stable on thin strips too
     n_ref = max(dims)
-    prob = OF.TVDProblem(GH, dims, Kn=Kn, Pr=Pr, g=g + (0.0,), cfl=cfl, n_ref=n_ref)
-    lat = TVDLattice(dims[0], dims[1], storage=storage, cfl=cfl, n_ref=n_ref)
+    kw = {}
+    if walls:
+        kw = dict(walls=True, wall_lo=OL.Wall(walls["T"][0], (walls["u"][0], 0.0, 0.0)),
+                  wall_hi=OL.Wall(walls["T"][1], (walls["u"][1], 0.0, 0.0)))
+    prob = OF.TVDProblem(GH, dims, Kn=Kn, Pr=Pr, g=g + (0.0,), cfl=cfl, n_ref=n_ref, **kw)
+    lat = TVDLattice(dims[0], dims[1], storage=storage, cfl=cfl, n_ref=n_ref, walls=bool(walls))
     assert lat.dt == pytest.approx(prob.dt, rel=1e-14)
     lat.set_gas(Kn, Pr)
     lat.set_body_force(g)
+    if walls:
+        for side in (0, 1):
+            lat.set_wall(side, walls["T"][side], (walls["u"][side], 0.0, 0.0))
     rho, u, T, xi, amp = H.init_fields(None, prob.M, 2, GH.Q, seed=seed, amp=amp)
     lat.init_equilibrium(rho, u, T, xi, amp)
     f = OF.equilibrium_state(prob, rho, u.T, T, xi, amp)
@@ -65,6 +79,47 @@ def test_tvd_step_parity(dims, storage):
     if storage == "f64":
         h, ho = lat.get_populations(), f / GH.w[:, None] - 1.0
         assert np.abs(h - ho).max() / np.abs(ho).max() < 1e-12
+
+
+@pytest.mark.parametrize("dims", CASES)
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_tvd_walls_parity(dims, storage):
+    """Sec. 3.2 walls on rows 0 and ny - 1 (moving, at different
+    temperatures): ghost rows, re-emission after every step."""
+    if dims[1] < 3:
+        pytest.skip("a channel needs three rows")
+    lat, prob, f = _pair(dims, storage, walls=WALLS)
+    lat.step(12)
+    f = OF.run(f, prob, 12)
+    ea, er = H.assert_parity(lat.read_moments(), _fields(f, prob), storage)
+    print(dims, storage, "walls: scale", max(ea.values()), "signal", max(er.values()))
+    if storage == "f64":
+        h, ho = lat.get_populations(), f / GH.w[:, None] - 1.0
+        assert np.abs(h - ho).max() / np.abs(ho).max() < 1e-12
+
+
+@pytest.mark.parametrize("case", ["couette", "fourier"])
+def test_tvd_walls_long_run_fp64(case):
+    # 300 steps of a 1 x 13 channel from rest: the profiles of Sec. 4
+    # build up through the walls alone
+    walls = dict(T=(1.0, 1.0), u=(-0.05, 0.05)) if case == "couette" else dict(T=(1.0, 1.1), u=(0.0, 0.0))
+    lat, prob, _ = _pair((1, 13), "f64", cfl=0.9, Kn=0.1, g=(0.0, 0.0), amp=0.0, walls=walls)
+    lat.init_equilibrium()
+    M = prob.M
+    f = OF.equilibrium_state(prob, np.ones(M), np.zeros((M, 2)), np.ones(M))
+    lat.step(300)
+    f = OF.run(f, prob, 300)
+    H.assert_parity(lat.read_moments(), _fields(f, prob), "f64")
+    h, ho = lat.get_populations(), f / GH.w[:, None] - 1.0
+    assert np.abs(h - ho).max() / np.abs(ho).max() < 1e-12
+
+
+def test_tvd_walls_wider_channel_fp32():
+    # several wavefronts per row, a ragged row end, 3 steps
+    lat, prob, f = _pair((520, 40), "f32", walls=WALLS, seed=7)
+    lat.step(3)
+    f = OF.run(f, prob, 3)
+    H.assert_parity(lat.read_moments(), _fields(f, prob), "f32")
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
@@ -185,7 +240,11 @@ def test_tvd_rejects_bad_arguments():
         TVDLattice(8, 8, storage="f32", cfl=1.5)
     with pytest.raises(EsbgkError):
         TVDLattice(8, 8, storage="f32", cfl=0.0)
+    with pytest.raises(EsbgkError):
+        TVDLattice(8, 2, storage="f32", walls=True)     # a channel needs three rows
     lat = TVDLattice(8, 8, storage="f32")
+    with pytest.raises(EsbgkError):
+        lat.set_wall(0, 1.0)            # no walls on this lattice
     with pytest.raises(EsbgkError):
         lat.step(1)                     # no state yet
     with pytest.raises(EsbgkError):
@@ -201,3 +260,7 @@ def test_tvd_rejects_bad_arguments():
         lat.step(-1)
     lat.step(1)
     assert lat.steps_done == 1
+    ch = TVDLattice(8, 8, storage="f32", walls=True)
+    for bad in ((2, 1.0, (0, 0, 0)), (0, -1.0, (0, 0, 0)), (0, 1.0, (0.0, 0.1, 0.0)), (1, np.inf, (0, 0, 0))):
+        with pytest.raises(EsbgkError):
+            ch.set_wall(*bad)
