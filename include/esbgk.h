@@ -60,7 +60,8 @@ enum {
 };
 
 enum { ESBGK_D2Q37 = 1, ESBGK_D3Q39 = 2,             /* on-lattice velocity sets */
-       ESBGK_D2Q36GH = 3 };                          /* 6-point Gauss-Hermite product set (esbgk_tvd_*) */
+       ESBGK_D2Q36GH = 3,                            /* 6-point Gauss-Hermite product set (esbgk_tvd_*) */
+       ESBGK_D2Q16GH = 4, ESBGK_D2Q64GH = 5 };       /* 4- and 8-point product sets (esbgk_tvd_*) */
 enum { ESBGK_F64 = 0, ESBGK_F32 = 1, ESBGK_F16 = 2 };  /* storage of h; FP64 computes in FP64, the others in FP32 */
 enum { ESBGK_TRAPEZOID = 0, ESBGK_EULER = 1 };         /* time discretisation of eq. lbgk */
 
@@ -250,7 +251,10 @@ const char* esbgk_batch_last_error(const esbgk_batch* b);
 /* ---- The paper's own scheme (Sec. 3.1) ----------------------------------
  * The velocity set of the paper: the tensor product of the 6-point
  * Gauss-Hermite rule of eq. weight (ESBGK_D2Q36GH: 36 velocities, exact to
- * degree 11 along each axis, carrying the N = 4 expansion). Its abscissae lie
+ * degree 11 along each axis, carrying the N = 4 expansion). For
+ * velocity-set convergence studies the 4-point (ESBGK_D2Q16GH: degree 7,
+ * N = 3) and 8-point (ESBGK_D2Q64GH: degree 15, N = 4) products run the
+ * same scheme. The abscissae lie
  * off the lattice, so streaming is the paper's finite-difference update:
  * forward Euler in time and, along each axis, the second-order TVD flux
  * difference with the minmod limiter,
@@ -260,7 +264,7 @@ const char* esbgk_batch_last_error(const esbgk_batch* b);
  * its mirror image (upwind cell i + 1) for c < 0. Every term is evaluated at
  * level n; one fused kernel launch per step. The stored state is the
  * physical f (deviational h = f/w - 1 in the storage type, in the velocity
- * order of esbgk_tvd_info).
+ * order of esbgk_tvd_set_info).
  *
  * Boundaries: periodic in x; in y periodic (walls = 0) or bounded by the
  * diffuse walls of Sec. 3.2 (walls = 1): rows 0 and ny - 1 lie on the
@@ -270,14 +274,20 @@ const char* esbgk_batch_last_error(const esbgk_batch* b);
  * normal flux toward the wall at the first row off it over that of S (a
  * second small kernel launch). Walls are fully diffuse at fixed T_W, u_W.
  *
- * Shape: velset = ESBGK_D2Q36GH, nz = 1, walls = 0 or 1 (ny >= 3),
+ * Shape: velset = ESBGK_D2Q16GH / D2Q36GH / D2Q64GH, nz = 1, walls = 0 or 1 (ny >= 3),
  * scheme = ESBGK_EULER, storage F64 / F32 / F16 (FP32 compute for the last
  * two), n_ref = N_L (0: nx, or the wall distance ny - 1 with walls). The
- * time step is dt = cfl dx / max|c| with dx = 1/N_L and 0 < cfl <= 1. */
+ * time step is dt = cfl dx / max|c| with dx = 1/N_L and 0 < cfl <= 1; the
+ * largest root, and so dt, depends on the set. */
 typedef struct esbgk_tvd esbgk_tvd;
 
-/* Abscissae c[36][2] and weights w[36] of ESBGK_D2Q36GH (either may be
- * NULL), derived on the host from the roots of He_6 and eq. weight. */
+/* Number of velocities Q, Hermite order N, abscissae c[Q][2] and weights
+ * w[Q] of a product set (any output may be NULL), derived on the host from
+ * the roots of He_n and eq. weight; the velocities are ordered by |c|^2,
+ * then by descending tuple of root indices, with the opposite of velocity
+ * a < Q/2 at a + Q/2. E_INVALID for another velset. */
+int esbgk_tvd_set_info(int velset, int* Q, int* N, double* c, double* w);
+/* esbgk_tvd_set_info of ESBGK_D2Q36GH: c[36][2], w[36]. */
 int esbgk_tvd_info(double* c, double* w);
 /* Device workspace bytes for the shape (0 if invalid). */
 size_t esbgk_tvd_workspace_bytes(const esbgk_shape* shape);
@@ -299,10 +309,10 @@ int esbgk_tvd_set_gas(esbgk_tvd* t, double Kn, double Pr, double varpi);
 int esbgk_tvd_set_wall(esbgk_tvd* t, int side, double T_w, const double u_w[3]);
 int esbgk_tvd_set_body_force(esbgk_tvd* t, const double g[3]);
 /* Initial state f = rho S(T, u) (1 + amplitude noise) as
- * esbgk_init_equilibrium (u is [2][cells], noise [36][cells]). */
+ * esbgk_init_equilibrium (u is [2][cells], noise [Q][cells]). */
 int esbgk_tvd_init_equilibrium(esbgk_tvd* t, const double* rho, const double* u, const double* T,
                                const double* noise, double amplitude);
-/* Stored populations as FP64 h[36][cells] (host); set rounds to the storage
+/* Stored populations as FP64 h[Q][cells] (host); set rounds to the storage
  * type and resets the step counter. */
 int esbgk_tvd_set_populations(esbgk_tvd* t, const double* h);
 int esbgk_tvd_get_populations(esbgk_tvd* t, double* h);

@@ -16,11 +16,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libesbgk.so")
 
 OK, E_INVALID, E_NOMEM, E_HIP, E_NONFINITE, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5, -6
-D2Q37, D3Q39, D2Q36GH = 1, 2, 3
+D2Q37, D3Q39, D2Q36GH, D2Q16GH, D2Q64GH = 1, 2, 3, 4, 5
 F64, F32, F16 = 0, 1, 2
 TRAPEZOID, EULER = 0, 1
 
 _VELSET = {"D2Q37": D2Q37, "D3Q39": D3Q39}
+_GH_SET = {"D2Q16GH": D2Q16GH, "D2Q36GH": D2Q36GH, "D2Q64GH": D2Q64GH}
 _STORAGE = {"f64": F64, "f32": F32, "f16": F16}
 _SCHEME = {"trapezoid": TRAPEZOID, "euler": EULER}
 _NAMES = {E_INVALID: "E_INVALID", E_NOMEM: "E_NOMEM", E_HIP: "E_HIP", E_NONFINITE: "E_NONFINITE",
@@ -98,6 +99,7 @@ def lib():
             "esbgk_batch_steps_done": (I64, [P]),
             "esbgk_batch_last_error": (ctypes.c_char_p, [P]),
             "esbgk_tvd_info": (I, [DP, DP]),
+            "esbgk_tvd_set_info": (I, [I, P, P, DP, DP]),
             "esbgk_tvd_workspace_bytes": (SZ, [P]),
             "esbgk_tvd_create": (I, [P, D, P, SZ, P, P]),
             "esbgk_tvd_destroy": (I, [P]),
@@ -390,32 +392,44 @@ class Batch:
         return h
 
 
-def tvd_velocity_set():
-    """Abscissae c[36][2] and weights w[36] of the 6-point Gauss-Hermite
-    product set of the paper's own scheme."""
-    c = np.empty((36, 2))
-    w = np.empty(36)
-    rc = lib().esbgk_tvd_info(_dp(c), _dp(w))
+def tvd_velocity_set(velset="D2Q36GH"):
+    """Abscissae c[Q][2] and weights w[Q] of a Gauss-Hermite product set of
+    the paper's own scheme (D2Q16GH, D2Q36GH: the paper's, D2Q64GH)."""
+    Q, N = ctypes.c_int(), ctypes.c_int()
+    vid = _GH_SET[velset]
+    rc = lib().esbgk_tvd_set_info(vid, ctypes.byref(Q), ctypes.byref(N), None, None)
     if rc:
-        raise EsbgkError(rc, "tvd_info")
+        raise EsbgkError(rc, "tvd_set_info")
+    c = np.empty((Q.value, 2))
+    w = np.empty(Q.value)
+    rc = lib().esbgk_tvd_set_info(vid, None, None, _dp(c), _dp(w))
+    if rc:
+        raise EsbgkError(rc, "tvd_set_info")
     return c, w
 
 
 class TVDLattice:
-    """The paper's own scheme (forward Euler, TVD minmod fluxes) on the
-    6-point Gauss-Hermite product set D2Q36: periodic in x, and in y
-    periodic or (walls=True) bounded by diffuse walls on rows 0 and ny - 1."""
+    """The paper's own scheme (forward Euler, TVD minmod fluxes) on a
+    Gauss-Hermite product set (the paper's D2Q36GH by default; D2Q16GH and
+    D2Q64GH for velocity-set studies): periodic in x, and in y periodic or
+    (walls=True) bounded by diffuse walls on rows 0 and ny - 1."""
 
-    Q, D, N = 36, 2, 4
+    D = 2
 
-    def __init__(self, nx=64, ny=64, storage="f32", cfl=0.5, n_ref=0, walls=False, device="cuda:0"):
+    def __init__(self, nx=64, ny=64, storage="f32", cfl=0.5, n_ref=0, walls=False, velset="D2Q36GH",
+                 device="cuda:0"):
         import torch
         self.device = torch.device(device)
         self.dims = (nx, ny)
         self.cells = nx * ny
         self.storage = storage
         self.walls = bool(walls)
-        self.shape = Shape(D2Q36GH, nx, ny, 1, int(self.walls), _STORAGE[storage], EULER, n_ref)
+        self.velset = velset
+        Q, N = ctypes.c_int(), ctypes.c_int()
+        if lib().esbgk_tvd_set_info(_GH_SET[velset], ctypes.byref(Q), ctypes.byref(N), None, None):
+            raise EsbgkError(E_INVALID, f"unknown set {velset}")
+        self.Q, self.N = Q.value, N.value
+        self.shape = Shape(_GH_SET[velset], nx, ny, 1, int(self.walls), _STORAGE[storage], EULER, n_ref)
         L = lib()
         nbytes = L.esbgk_tvd_workspace_bytes(ctypes.byref(self.shape))
         if nbytes == 0:
@@ -427,7 +441,7 @@ class TVDLattice:
         if rc:
             msg = L.esbgk_tvd_last_error(None)
             raise EsbgkError(rc, f"tvd_create: {msg.decode() if msg else ''}")
-        self.c, self.w = tvd_velocity_set()
+        self.c, self.w = tvd_velocity_set(velset)
 
     def _check(self, rc, what):
         if rc:

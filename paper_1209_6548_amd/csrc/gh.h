@@ -1,43 +1,129 @@
-// The paper's own velocity set and scheme (Sec. 2.2, Sec. 3.1): the tensor
-// product of the 6-point Gauss-Hermite rule of eq. weight (exact to degree
-// 11 along each axis, carrying the N = 4 expansion), with forward Euler in
-// time and TVD minmod finite-volume fluxes in space.
+// The paper's own velocity sets and scheme (Sec. 2.2, Sec. 3.1): tensor
+// products of the n-point Gauss-Hermite rule of eq. weight (exact to degree
+// 2n - 1 along each axis), with forward Euler in time and TVD minmod
+// finite-volume fluxes in space. The paper's set is n = 6 (degree 11,
+// carrying the N = 4 expansion); n = 4 (degree 7, N = 3) and n = 8 (degree
+// 15, N = 4) bracket it for velocity-set convergence studies.
 //
-// The abscissae are off the lattice. Velocity alpha of the 2-D set is
-// (xi_{kx}, xi_{ky}) with signed root ranks k: xi_{+-1} = +-0.617...,
-// xi_{+-2} = +-1.889..., xi_{+-3} = +-3.324.... The root values and weights
-// are derived on the host at start-up; here only the ranks are compile-time.
+// The abscissae are off the lattice. Velocity alpha of a 2-D set is
+// (xi_{kx}, xi_{ky}) with signed root ranks k in +-1..+-n/2 (xi_{+-1} the
+// positive and negative roots nearest zero). The root values and weights are
+// derived on the host at start-up; here only the ranks and their order are
+// compile-time.
 //
-// Velocity order (shared with the population I/O): the 18 representatives
-// (first component positive) sorted by |c|^2 and then by descending rank
-// tuple, followed by their opposites at alpha + 18.
+// Velocity order (shared with the population I/O): the representatives
+// (first component positive) sorted by |c|^2 and then by descending tuple of
+// root indices (root index = position of the root in ascending order), then
+// their opposites at alpha + P.
 #pragma once
 
 #include "cell.h"
 
 namespace esbgk {
 
-struct D2Q36GH {
+// He_n(x) by the three-term recurrence He_{k+1} = x He_k - k He_{k-1}.
+constexpr double gh_he(int n, double x) {
+  double a = 1.0, b = x;
+  if (n == 0) return a;
+  for (int k = 1; k < n; ++k) {
+    const double c = x * b - double(k) * a;
+    a = b;
+    b = c;
+  }
+  return b;
+}
+
+// The m-th positive root of He_n (m = 1..n/2, ascending), by a sign scan from
+// 0 and bisection: accurate enough to order the velocities (|c|^2 of
+// distinct shells differ by more than 0.1 for n <= 8).
+constexpr double gh_root(int n, int m) {
+  const double step = 1.0 / 64;
+  double x = 0.0, fx = gh_he(n, 0.0);
+  int found = 0;
+  for (int i = 0; i < 64 * 8; ++i) {
+    const double y = x + step, fy = gh_he(n, y);
+    if ((fx < 0) != (fy < 0) && ++found == m) {
+      double lo = x, hi = y;
+      for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if ((gh_he(n, mid) < 0) == (fx < 0)) lo = mid;
+        else hi = mid;
+      }
+      return 0.5 * (lo + hi);
+    }
+    x = y;
+    fx = fy;
+  }
+  return -1.0;
+}
+
+// The tensor product of the n-point rule in 2-D.
+template <int NPTS>
+struct GHSet {
+  static_assert(NPTS % 2 == 0 && NPTS >= 4 && NPTS <= 8, "even rules of 4 to 8 points");
+  static constexpr int n = NPTS;
+  static constexpr int H = NPTS / 2;           // positive roots per axis
   static constexpr int D = 2;
-  static constexpr int Q = 36;
-  static constexpr int P = 18;
-  static constexpr int N = 4;
-  static constexpr int K[P][2] = {
-      {1, 1},  {1, -1},  {2, 1},  {2, -1},  {1, 2},  {1, -2},  {2, 2},  {2, -2},  {3, 1},
-      {3, -1}, {1, 3},   {1, -3}, {3, 2},   {3, -2}, {2, 3},   {2, -3}, {3, 3},   {3, -3},
+  static constexpr int Q = NPTS * NPTS;
+  static constexpr int P = Q / 2;
+  static constexpr int N = NPTS >= 6 ? 4 : 3;  // Hermite order the set carries (2N + 1 <= 2n - 1)
+  struct Ranks {
+    int K[P][2];
   };
+  // root index of signed rank k: 0..n-1 in ascending root order
+  static constexpr int index(int k) { return k > 0 ? H + k - 1 : H + k; }
+  static constexpr Ranks make_ranks() {
+    Ranks t{};
+    double r[H + 1] = {};
+    for (int m = 1; m <= H; ++m) r[m] = gh_root(NPTS, m);
+    int cnt = 0;
+    for (int k1 = 1; k1 <= H; ++k1)
+      for (int k2 = -H; k2 <= H; ++k2)
+        if (k2 != 0) {
+          t.K[cnt][0] = k1;
+          t.K[cnt][1] = k2;
+          ++cnt;
+        }
+    auto c2 = [&r](const int* k) {
+      const double a = r[k[0] < 0 ? -k[0] : k[0]], b = r[k[1] < 0 ? -k[1] : k[1]];
+      return a * a + b * b;
+    };
+    auto before = [&](const int* u, const int* v) {
+      const double cu = c2(u), cv = c2(v);
+      if (cu != cv) return cu < cv;
+      if (index(u[0]) != index(v[0])) return index(u[0]) > index(v[0]);
+      return index(u[1]) > index(v[1]);
+    };
+    for (int i = 1; i < P; ++i)          // insertion sort
+      for (int j = i; j > 0 && before(t.K[j], t.K[j - 1]); --j) {
+        const int a0 = t.K[j][0], a1 = t.K[j][1];
+        t.K[j][0] = t.K[j - 1][0];
+        t.K[j][1] = t.K[j - 1][1];
+        t.K[j - 1][0] = a0;
+        t.K[j - 1][1] = a1;
+      }
+    return t;
+  }
+  static constexpr Ranks ranks = make_ranks();
 };
 
-// Sign of component i of velocity alpha (alpha < 36).
+using D2Q16GH = GHSet<4>;
+using D2Q36GH = GHSet<6>;
+using D2Q64GH = GHSet<8>;
+
+// Sign of component i of velocity alpha of set L.
+template <class L>
 __host__ __device__ constexpr int gh_sign(int alpha, int i) {
-  return (alpha < D2Q36GH::P ? 1 : -1) * (D2Q36GH::K[alpha % D2Q36GH::P][i] > 0 ? 1 : -1);
+  return (alpha < L::P ? 1 : -1) * (L::ranks.K[alpha % L::P][i] > 0 ? 1 : -1);
 }
 
 // Number of monomials c^n, n = 1..4, of a 2-D velocity: x y | xx xy yy |
 // xxx xxy xyy yyy | xxxx xxxy xxyy xyyy yyyy.
 constexpr int GH_MONO = 14;
+constexpr int GH_PMAX = 32;   // representatives of the largest set
 
-// Per-set constants of the scheme (device memory, built on the host):
+// Per-set constants of the scheme (device memory, built on the host), for
+// the representatives p < P of the set:
 //   w     weight of representative p (its opposite has the same weight)
 //   mono  the 14 monomials of representative p (the opposite's odd ones
 //         change sign)
@@ -47,18 +133,18 @@ constexpr int GH_MONO = 14;
 //         flux difference (the same for the opposite velocity)
 template <typename C>
 struct GHConsts {
-  C w[D2Q36GH::P];
-  C mono[D2Q36GH::P][GH_MONO];
-  C nu[D2Q36GH::P][2];
-  C nk[D2Q36GH::P][2];
+  C w[GH_PMAX];
+  C mono[GH_PMAX][GH_MONO];
+  C nu[GH_PMAX][2];
+  C nk[GH_PMAX][2];
 };
 
 // Raw moments sum w h (1, c, cc, ccc) of the deviational h over the set,
 // from the (alpha, alpha + P) pair sums and differences.
-template <typename C>
-__device__ __forceinline__ void raw_moments_gh(const C (&h)[D2Q36GH::Q], const GHConsts<C>* __restrict__ g,
-                                               bool third, RawMoments<D2Q36GH, C>& m) {
-  constexpr int P = D2Q36GH::P;
+template <class L, typename C>
+__device__ __forceinline__ void raw_moments_gh(const C (&h)[L::Q], const GHConsts<C>* __restrict__ g,
+                                               bool third, RawMoments<L, C>& m) {
+  constexpr int P = L::P;
   m.drho = C(0);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -111,13 +197,12 @@ struct GHCollision {
   C K0, K1[2], k2[3], k3[4], k4[5], omw;
 };
 
-template <typename C>
-__device__ __forceinline__ void collision_gh(const C (&h)[D2Q36GH::Q], const GHConsts<C>* __restrict__ g,
+template <class L, typename C>
+__device__ __forceinline__ void collision_gh(const C (&h)[L::Q], const GHConsts<C>* __restrict__ g,
                                              const LatConsts<C>* __restrict__ lc,
                                              const ProbParams<C>* __restrict__ pp, GHCollision<C>& k) {
-  using L = D2Q36GH;
   RawMoments<L, C> m;
-  raw_moments_gh<C>(h, g, pp->force != 0, m);
+  raw_moments_gh<L, C>(h, g, pp->force != 0 && L::N >= 4, m);
   CellState<L, C> s;
   reconstruct<L, C>(m, lc, pp, s);
   C K0, K1[3], K2[3][3], K3[3][3][3], K4[3][3][3][3];
@@ -132,17 +217,22 @@ __device__ __forceinline__ void collision_gh(const C (&h)[D2Q36GH::Q], const GHC
   k.k3[1] = C(3) * K3[0][0][1];
   k.k3[2] = C(3) * K3[0][1][1];
   k.k3[3] = K3[1][1][1];
-  k.k4[0] = K4[0][0][0][0];
-  k.k4[1] = C(4) * K4[0][0][0][1];
-  k.k4[2] = C(6) * K4[0][0][1][1];
-  k.k4[3] = C(4) * K4[0][1][1][1];
-  k.k4[4] = K4[1][1][1][1];
+  if constexpr (L::N >= 4) {
+    k.k4[0] = K4[0][0][0][0];
+    k.k4[1] = C(4) * K4[0][0][0][1];
+    k.k4[2] = C(6) * K4[0][0][1][1];
+    k.k4[3] = C(4) * K4[0][1][1][1];
+    k.k4[4] = K4[1][1][1][1];
+  } else {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) k.k4[j] = C(0);
+  }
   k.omw = C(1) - s.omega;
 }
 
 // Post-collision values of the pair (p, p + P) from their pre-collision
-// values hp, hm.
-template <typename C>
+// values hp, hm (the quartic terms only for a set carrying N = 4).
+template <class L, typename C>
 __device__ __forceinline__ void collide_pair_gh(const GHCollision<C>& k, const C* __restrict__ mo, C hp, C hm,
                                                 C& outp, C& outm) {
   C E = k.K0, O = C(0);
@@ -152,33 +242,34 @@ __device__ __forceinline__ void collide_pair_gh(const GHCollision<C>& k, const C
   for (int j = 0; j < 3; ++j) E = fmac(k.k2[j], mo[2 + j], E);
 #pragma unroll
   for (int j = 0; j < 4; ++j) O = fmac(k.k3[j], mo[5 + j], O);
+  if constexpr (L::N >= 4) {
 #pragma unroll
-  for (int j = 0; j < 5; ++j) E = fmac(k.k4[j], mo[9 + j], E);
+    for (int j = 0; j < 5; ++j) E = fmac(k.k4[j], mo[9 + j], E);
+  }
   outp = fmac(k.omw, hp, E + O);
   outm = fmac(k.omw, hm, E - O);
 }
 
 // The collision of every velocity in place.
-template <typename C>
-__device__ __forceinline__ void collide_gh(C (&h)[D2Q36GH::Q], const GHConsts<C>* __restrict__ g,
+template <class L, typename C>
+__device__ __forceinline__ void collide_gh(C (&h)[L::Q], const GHConsts<C>* __restrict__ g,
                                            const LatConsts<C>* __restrict__ lc,
                                            const ProbParams<C>* __restrict__ pp) {
-  constexpr int P = D2Q36GH::P;
+  constexpr int P = L::P;
   GHCollision<C> k;
-  collision_gh<C>(h, g, lc, pp, k);
+  collision_gh<L, C>(h, g, lc, pp, k);
 #pragma unroll
-  for (int p = 0; p < P; ++p) collide_pair_gh<C>(k, g->mono[p], h[p], h[p + P], h[p], h[p + P]);
+  for (int p = 0; p < P; ++p) collide_pair_gh<L, C>(k, g->mono[p], h[p], h[p + P], h[p], h[p + P]);
 }
 
 // rho, u[2], T, sigma (xx, xy, yy), q[2] of the stored (physical) f.
-template <typename C>
-__device__ __forceinline__ void cell_fields_gh(const C (&h)[D2Q36GH::Q], const GHConsts<C>* __restrict__ g,
+template <class L, typename C>
+__device__ __forceinline__ void cell_fields_gh(const C (&h)[L::Q], const GHConsts<C>* __restrict__ g,
                                                const LatConsts<C>* __restrict__ lc,
                                                const ProbParams<C>* __restrict__ pp, double* out) {
-  using L = D2Q36GH;
   constexpr int D = 2;
   RawMoments<L, C> m;
-  raw_moments_gh<C>(h, g, true, m);
+  raw_moments_gh<L, C>(h, g, true, m);
   CellState<L, C> s;
   reconstruct<L, C>(m, lc, pp, s);
   C A3[3][3][3], a2[3][3], a3[3][3][3];

@@ -298,34 +298,46 @@ static bool gauss_hermite_rule(int n, std::vector<ld>& x, std::vector<ld>& w) {
   return true;
 }
 
-const HostGH* host_gh() {
-  static HostGH gh;
-  static bool ok = false;
-  static std::once_flag once;
-  std::call_once(once, [&]() {
-    std::vector<ld> x, w;
-    if (!gauss_hermite_rule(6, x, w)) return;
-    // symmetric rule: positive roots x[3..5]; rank k in {+-1,+-2,+-3} means
-    // sign(k) * xi[|k| - 1]
-    ld xi[3], w1[3];
-    for (int m = 0; m < 3; ++m) {
-      xi[m] = 0.5L * (x[3 + m] - x[2 - m]);   // average the mirrored pair
-      w1[m] = 0.5L * (w[3 + m] + w[2 - m]);
-      gh.xi[m] = double(xi[m]);
+template <class L>
+static bool build_gh(HostGH& gh) {
+  std::vector<ld> x, w;
+  if (!gauss_hermite_rule(L::n, x, w)) return false;
+  constexpr int H = L::H;
+  // symmetric rule: positive roots x[H..n-1]; rank k in +-1..+-H means
+  // sign(k) * xi[|k| - 1]
+  ld xi[4], w1[4];
+  for (int m = 0; m < H; ++m) {
+    xi[m] = 0.5L * (x[H + m] - x[H - 1 - m]);   // average the mirrored pair
+    w1[m] = 0.5L * (w[H + m] + w[H - 1 - m]);
+    gh.xi[m] = double(xi[m]);
+  }
+  gh.n = L::n;
+  gh.Q = L::Q;
+  gh.P = L::P;
+  gh.N = L::N;
+  for (int a = 0; a < L::Q; ++a) {
+    ld wa = 1;
+    for (int i = 0; i < 2; ++i) {
+      const int k = L::ranks.K[a % L::P][i] * (a < L::P ? 1 : -1);
+      const int m = (k < 0 ? -k : k) - 1;
+      gh.c[a][i] = double(k < 0 ? -xi[m] : xi[m]);
+      wa *= w1[m];
     }
-    for (int a = 0; a < 36; ++a) {
-      ld wa = 1;
-      for (int i = 0; i < 2; ++i) {
-        const int k = D2Q36GH::K[a % 18][i] * (a < 18 ? 1 : -1);
-        const int m = (k < 0 ? -k : k) - 1;
-        gh.c[a][i] = double(k < 0 ? -xi[m] : xi[m]);
-        wa *= w1[m];
-      }
-      gh.w[a] = double(wa);
-    }
-    ok = true;
+    gh.w[a] = double(wa);
+  }
+  return true;
+}
+
+const HostGH* host_gh(int n) {
+  static HostGH tabs[3];
+  static bool ok[3] = {false, false, false};
+  static std::once_flag once[3];
+  const int i = n == 4 ? 0 : (n == 6 ? 1 : (n == 8 ? 2 : -1));
+  if (i < 0) return nullptr;
+  std::call_once(once[i], [&]() {
+    ok[i] = n == 4 ? build_gh<D2Q16GH>(tabs[i]) : (n == 6 ? build_gh<D2Q36GH>(tabs[i]) : build_gh<D2Q64GH>(tabs[i]));
   });
-  return ok ? &gh : nullptr;
+  return ok[i] ? &tabs[i] : nullptr;
 }
 
 // S(T, u)(c) / w - 1 at the velocity c[D]: eq. feq0 with rho = 1, truncated

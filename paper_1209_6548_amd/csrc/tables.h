@@ -19,16 +19,18 @@ struct HostLattice {
 // Derived once per process; null if the derivation failed.
 const HostLattice* host_lattice(int velset);
 
-// The 6-point Gauss-Hermite product set D2Q36 of the paper's own scheme:
-// positive roots xi[0..2] of He_6 (ascending), and per velocity (in the order
-// of D2Q36GH) the abscissae c[a][2] and weights w[a]. Derived once per
-// process; null if the derivation failed.
+// The n-point Gauss-Hermite product set of the paper's own scheme (n = 4, 6
+// or 8: D2Q16, D2Q36, D2Q64): positive roots xi[0..n/2-1] of He_n
+// (ascending), and per velocity (in the order of GHSet<n>) the abscissae
+// c[a][2] and weights w[a]. Derived once per process and set; null if the
+// derivation failed or n is not one of those.
 struct HostGH {
-  double xi[3];
-  double c[36][2];
-  double w[36];
+  int n, Q, P, N;
+  double xi[4];
+  double c[64][2];
+  double w[64];
 };
-const HostGH* host_gh();
+const HostGH* host_gh(int n);
 
 // S(T, u)/w - 1 at velocity a (eq. feq0, rho = 1, order N of the lattice).
 double shat_minus_one(const HostLattice& lat, int a, double T, const double u[3]);

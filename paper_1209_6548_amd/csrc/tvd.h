@@ -14,7 +14,7 @@ struct TVDArgs {
   Geometry geo;
   const void* src;   // populations read (storage type, slice layout)
   void* dst;         // populations written
-  const void* gc;    // GHConsts<C>*    of the compute type
+  const void* gc;    // GHConsts<C>*    of the compute type (the set's P entries used)
   const void* lc;    // LatConsts<C>*   (w, r = 1)
   const void* pp;    // ProbParams<C>*  (Euler: hs = hsdt = 0)
   const void* gc64;  // FP64 blocks for the read-out and init kernels
@@ -33,16 +33,19 @@ struct TVDArgs {
 //              (the wall node's new h_a is rho_W sw - 1), 0 for the others
 template <typename C>
 struct TVDWalls {
-  C kin[2][36];
+  C kin[2][64];
   C k0[2];
-  C sw[2][36];
+  C sw[2][64];
 };
 
-hipError_t launch_tvd_step(int storage, const TVDArgs& a);
+// velset: ESBGK_D2Q16GH / ESBGK_D2Q36GH / ESBGK_D2Q64GH; storage: 0 FP64,
+// 1 FP32, 2 FP16.
+hipError_t launch_tvd_step(int velset, int storage, const TVDArgs& a);
 // Re-emission at both walls into a.dst (the level just written by the step).
-hipError_t launch_tvd_walls(int storage, const TVDArgs& a, const void* walls);
-hipError_t launch_tvd_init(int storage, const TVDArgs& a, const double* c, const double* rho, const double* u,
-                           const double* T, const double* noise, double amp, uint32_t c0, uint32_t count);
-hipError_t launch_tvd_moments(int storage, const TVDArgs& a, uint32_t c0, uint32_t count, double* out);
+hipError_t launch_tvd_walls(int velset, int storage, const TVDArgs& a, const void* walls);
+hipError_t launch_tvd_init(int velset, int storage, const TVDArgs& a, const double* c, const double* rho,
+                           const double* u, const double* T, const double* noise, double amp, uint32_t c0,
+                           uint32_t count);
+hipError_t launch_tvd_moments(int velset, int storage, const TVDArgs& a, uint32_t c0, uint32_t count, double* out);
 
 }  // namespace esbgk

@@ -19,7 +19,12 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr uint32_t STAGE_CELLS = 65536;
-constexpr int QGH = D2Q36GH::Q;
+constexpr int QGH_MAX = 64;
+
+// Points of the 1-D rule of a product set (0: not a set of this scheme).
+int set_points(int velset) {
+  return velset == ESBGK_D2Q16GH ? 4 : (velset == ESBGK_D2Q36GH ? 6 : (velset == ESBGK_D2Q64GH ? 8 : 0));
+}
 constexpr int NFIELDS = 9;
 
 size_t align_up(size_t n) { return (n + ALIGN - 1) / ALIGN * ALIGN; }
@@ -33,16 +38,17 @@ struct TLayout {
 bool valid_tvd_shape(const esbgk_shape* s, Geometry* g, std::string* why) {
   auto fail = [&](const char* m) { if (why) *why = m; return false; };
   if (!s) return fail("null shape");
-  if (s->velset != ESBGK_D2Q36GH) return fail("velset must be ESBGK_D2Q36GH");
+  if (!set_points(s->velset)) return fail("velset must be ESBGK_D2Q16GH, ESBGK_D2Q36GH or ESBGK_D2Q64GH");
   if (s->nx < 1 || s->ny < 1 || s->nz != 1) return fail("extents: nx, ny >= 1 and nz = 1");
   if (s->walls != 0 && s->walls != 1) return fail("walls must be 0 (periodic) or 1 (walls across y)");
   if (s->walls && s->ny < 3) return fail("a channel needs ny >= 3 (two wall rows and one between)");
   if (s->storage < ESBGK_F64 || s->storage > ESBGK_F16) return fail("storage must be F64, F32 or F16");
   if (s->scheme != ESBGK_EULER) return fail("the paper's scheme is forward Euler (scheme = ESBGK_EULER)");
   if (s->n_ref < 0) return fail("n_ref must be >= 0");
-  if (!host_gh()) return fail("velocity set tables unavailable");
+  const HostGH* gh = host_gh(set_points(s->velset));
+  if (!gh) return fail("velocity set tables unavailable");
   Geometry tmp;
-  if (!make_geometry(2, QGH, uint32_t(s->nx), uint32_t(s->ny), 1, s->walls != 0, true, ssize(s->storage),
+  if (!make_geometry(2, gh->Q, uint32_t(s->nx), uint32_t(s->ny), 1, s->walls != 0, true, ssize(s->storage),
                      g ? *g : tmp))
     return fail("lattice too large for the slice layout (one row of populations must be < 4 GiB)");
   return true;
@@ -63,9 +69,9 @@ TLayout tlayout(const esbgk_shape* s, const Geometry& g) {
   L.lc64 = cs == 8 ? L.lc : take(sizeof(LatConsts<double>));
   L.pp64 = cs == 8 ? L.pp : take(sizeof(ProbParams<double>));
   L.walls = take(cs == 8 ? sizeof(TVDWalls<double>) : sizeof(TVDWalls<float>));
-  L.c = take(sizeof(double) * QGH * 2);
+  L.c = take(sizeof(double) * QGH_MAX * 2);
   const size_t stage = std::min<size_t>(cells, STAGE_CELLS);
-  L.staging = take(stage * size_t(std::max(NFIELDS, 4 + QGH)) * sizeof(double));
+  L.staging = take(stage * size_t(std::max(NFIELDS, 4 + QGH_MAX)) * sizeof(double));
   L.total = off;
   return L;
 }
@@ -73,7 +79,7 @@ TLayout tlayout(const esbgk_shape* s, const Geometry& g) {
 template <typename C>
 void pack_gh(const HostGH& gh, double nu_scale, GHConsts<C>& d) {
   std::memset(&d, 0, sizeof(d));
-  for (int p = 0; p < D2Q36GH::P; ++p) {
+  for (int p = 0; p < gh.P; ++p) {
     const double x = gh.c[p][0], y = gh.c[p][1];
     const double m[GH_MONO] = {x,         y,         x * x,         x * y,         y * y,
                                x * x * x, x * x * y, x * y * y,     y * y * y,     x * x * x * x,
@@ -94,14 +100,14 @@ void pack_walls(const HostGH& gh, const double Tw[2], const double uw[2][3], TVD
   std::memset(&d, 0, sizeof(d));
   for (int side = 0; side < 2; ++side) {
     const double nrm = side == 0 ? 1.0 : -1.0;   // inward normal along y
-    double den = 0.0, sw[QGH];
-    for (int a = 0; a < QGH; ++a) {
-      sw[a] = 1.0 + shat_minus_one_at(2, 4, gh.c[a], Tw[side], uw[side]);
+    double den = 0.0, sw[QGH_MAX];
+    for (int a = 0; a < gh.Q; ++a) {
+      sw[a] = 1.0 + shat_minus_one_at(2, gh.N, gh.c[a], Tw[side], uw[side]);
       const double cn = nrm * gh.c[a][1];
       if (cn > 0) den += cn * gh.w[a] * sw[a];
     }
     double k0 = 0.0;
-    for (int a = 0; a < QGH; ++a) {
+    for (int a = 0; a < gh.Q; ++a) {
       const double cn = nrm * gh.c[a][1];
       if (cn < 0) {
         const double k = -cn * gh.w[a] / den;
@@ -130,6 +136,7 @@ struct esbgk_tvd {
   std::string err;
   double Kn = 0.1, Pr = 1.0, varpi = 0.5, cfl = 0.5, dt = 0.0, dx = 0.0;
   double g[3] = {0, 0, 0};
+  const HostGH* gh = nullptr;   // the velocity set's host tables
   double Tw[2] = {1.0, 1.0};
   double uw[2][3] = {{0, 0, 0}, {0, 0, 0}};
   char* at(size_t off) const { return ws + off; }
@@ -180,7 +187,7 @@ TVDArgs targs(const esbgk_tvd* c) {
 
 // Gas, force and the Courant-limited time step: dt = CFL dx / max|c|.
 int upload_tvd(esbgk_tvd* c) {
-  const HostGH& gh = *host_gh();
+  const HostGH& gh = *c->gh;
   HostProblem hp{};
   hp.dt = c->dt;
   hp.hs = 0.0;
@@ -202,19 +209,17 @@ int upload_tvd(esbgk_tvd* c) {
   static thread_local GHConsts<float> g32;
   static thread_local LatConsts<double> l64;
   static thread_local LatConsts<float> l32;
-  pack_params<double>(hp, QGH, pp64);
+  pack_params<double>(hp, 0, pp64);   // the wall tables of ProbParams are not used here
   pack_gh<double>(gh, nu_scale, g64);
   std::memset(&l64, 0, sizeof(l64));
-  for (int a = 0; a < QGH; ++a) l64.w[a] = gh.w[a];
-  l64.r = 1.0;
+  l64.r = 1.0;                        // the weights live in GHConsts
   TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.pp64), &pp64, sizeof(pp64), hipMemcpyHostToDevice, c->stream), "upload");
   TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.gc64), &g64, sizeof(g64), hipMemcpyHostToDevice, c->stream), "upload");
   TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.lc64), &l64, sizeof(l64), hipMemcpyHostToDevice, c->stream), "upload");
   if (!c->f64()) {
-    pack_params<float>(hp, QGH, pp32);
+    pack_params<float>(hp, 0, pp32);
     pack_gh<float>(gh, nu_scale, g32);
     std::memset(&l32, 0, sizeof(l32));
-    for (int a = 0; a < QGH; ++a) l32.w[a] = float(gh.w[a]);
     l32.r = 1.0f;
     TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.pp), &pp32, sizeof(pp32), hipMemcpyHostToDevice, c->stream), "upload");
     TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.gc), &g32, sizeof(g32), hipMemcpyHostToDevice, c->stream), "upload");
@@ -266,10 +271,13 @@ hipError_t tplane_to_host(esbgk_tvd* c, int q, void* host) {
 
 extern "C" {
 
-int esbgk_tvd_info(double* c, double* w) {
-  const HostGH* gh = host_gh();
+int esbgk_tvd_set_info(int velset, int* Q, int* N, double* c, double* w) {
+  const int n = set_points(velset);
+  const HostGH* gh = n ? host_gh(n) : nullptr;
   if (!gh) return ESBGK_E_INVALID;
-  for (int a = 0; a < QGH; ++a) {
+  if (Q) *Q = gh->Q;
+  if (N) *N = gh->N;
+  for (int a = 0; a < gh->Q; ++a) {
     if (c) {
       c[2 * a] = gh->c[a][0];
       c[2 * a + 1] = gh->c[a][1];
@@ -278,6 +286,8 @@ int esbgk_tvd_info(double* c, double* w) {
   }
   return ESBGK_OK;
 }
+
+int esbgk_tvd_info(double* c, double* w) { return esbgk_tvd_set_info(ESBGK_D2Q36GH, nullptr, nullptr, c, w); }
 
 size_t esbgk_tvd_workspace_bytes(const esbgk_shape* shape) {
   Geometry g;
@@ -313,10 +323,11 @@ int esbgk_tvd_create(const esbgk_shape* shape, double cfl, void* d_workspace, si
   c->cfl = cfl;
   const int n_ref = shape->n_ref > 0 ? shape->n_ref : (shape->walls ? shape->ny - 1 : shape->nx);
   c->dx = 1.0 / double(n_ref);
-  const HostGH& gh = *host_gh();
-  c->dt = cfl * c->dx / gh.xi[2];
-  double cc[QGH * 2];
-  for (int a = 0; a < QGH; ++a) {
+  c->gh = host_gh(set_points(shape->velset));
+  const HostGH& gh = *c->gh;
+  c->dt = cfl * c->dx / gh.xi[gh.n / 2 - 1];
+  double cc[QGH_MAX * 2] = {};
+  for (int a = 0; a < gh.Q; ++a) {
     cc[2 * a] = gh.c[a][0];
     cc[2 * a + 1] = gh.c[a][1];
   }
@@ -407,10 +418,10 @@ int esbgk_tvd_init_equilibrium(esbgk_tvd* c, const double* rho, const double* u,
                                   c->stream), "stage");
     if (T) TVD_HIP(c, hipMemcpyAsync(d_T, T + c0, n * 8, hipMemcpyHostToDevice, c->stream), "stage");
     if (noise)
-      for (int q = 0; q < QGH; ++q)
+      for (int q = 0; q < c->gh->Q; ++q)
         TVD_HIP(c, hipMemcpyAsync(d_noise + size_t(q) * n, noise + size_t(q) * cells + c0, n * 8,
                                   hipMemcpyHostToDevice, c->stream), "stage");
-    TVD_HIP(c, launch_tvd_init(c->shape.storage, a, dc, rho ? d_rho : nullptr, u ? d_u : nullptr,
+    TVD_HIP(c, launch_tvd_init(c->shape.velset, c->shape.storage, a, dc, rho ? d_rho : nullptr, u ? d_u : nullptr,
                                T ? d_T : nullptr, noise ? d_noise : nullptr, amplitude, c0, n), "init");
     TVD_HIP(c, hipStreamSynchronize(c->stream), "init");
   }
@@ -424,7 +435,7 @@ int esbgk_tvd_set_populations(esbgk_tvd* c, const double* h) {
   if (!h) return tset_err(c, ESBGK_E_INVALID, "h is null");
   const size_t cells = c->geo.ncells;
   std::vector<unsigned char> buf;
-  for (int q = 0; q < QGH; ++q) {
+  for (int q = 0; q < c->gh->Q; ++q) {
     const double* src = h + size_t(q) * cells;
     const void* p = src;
     if (c->shape.storage == ESBGK_F32) {
@@ -449,7 +460,7 @@ int esbgk_tvd_get_populations(esbgk_tvd* c, double* h) {
   const size_t cells = c->geo.ncells, ss = ssize(c->shape.storage);
   std::vector<unsigned char> buf(cells * ss);
   TVD_HIP(c, hipStreamSynchronize(c->stream), "get populations");
-  for (int q = 0; q < QGH; ++q) {
+  for (int q = 0; q < c->gh->Q; ++q) {
     TVD_HIP(c, tplane_to_host(c, q, buf.data()), "get populations");
     TVD_HIP(c, hipStreamSynchronize(c->stream), "get populations");
     double* o = h + size_t(q) * cells;
@@ -466,8 +477,9 @@ int esbgk_tvd_step(esbgk_tvd* c, int64_t n) {
   if (!c->state_set) return tset_err(c, ESBGK_E_STATE, "no state set");
   for (int64_t k = 0; k < n; ++k) {
     const TVDArgs a = targs(c);
-    TVD_HIP(c, launch_tvd_step(c->shape.storage, a), "step");
-    if (c->shape.walls) TVD_HIP(c, launch_tvd_walls(c->shape.storage, a, c->at(c->lay.walls)), "walls");
+    TVD_HIP(c, launch_tvd_step(c->shape.velset, c->shape.storage, a), "step");
+    if (c->shape.walls)
+      TVD_HIP(c, launch_tvd_walls(c->shape.velset, c->shape.storage, a, c->at(c->lay.walls)), "walls");
     c->cur ^= 1;
     c->steps += 1;
   }
@@ -485,7 +497,7 @@ int esbgk_tvd_read_moments(esbgk_tvd* c, double* h_out, int* F) {
   const TVDArgs a = targs(c);
   for (uint32_t c0 = 0; c0 < cells; c0 += STAGE_CELLS) {
     const uint32_t n = std::min(STAGE_CELLS, cells - c0);
-    TVD_HIP(c, launch_tvd_moments(c->shape.storage, a, c0, n, st), "moments");
+    TVD_HIP(c, launch_tvd_moments(c->shape.velset, c->shape.storage, a, c0, n, st), "moments");
     tmp.resize(size_t(NFIELDS) * n);
     TVD_HIP(c, hipMemcpyAsync(tmp.data(), st, tmp.size() * 8, hipMemcpyDeviceToHost, c->stream), "moments");
     TVD_HIP(c, hipStreamSynchronize(c->stream), "moments");

@@ -90,16 +90,29 @@ def test_fast_division_constants():
             assert q == n // d, (d, n)
 
 
-def test_tvd_set_equals_the_oracle_product_set():
+@pytest.mark.parametrize("name,n,N", [("D2Q16GH", 4, 3), ("D2Q36GH", 6, 4), ("D2Q64GH", 8, 4)])
+def test_tvd_set_equals_the_oracle_product_set(name, n, N):
     from oracle import offlattice
+    from paper_1209_6548_amd import binding as B
     from paper_1209_6548_amd import tvd_velocity_set
-    c, w = tvd_velocity_set()
-    vs = offlattice.ProductSet(6, 2, 4)
-    # both sides round the 50-digit (oracle) or long-double (library) roots
+    c, w = tvd_velocity_set(name)
+    vs = offlattice.ProductSet(n, 2, N)
+    # same order; both sides round the 50-digit (oracle) or long-double
+    # (library) roots
     np.testing.assert_array_equal(c, vs.c)
-    np.testing.assert_allclose(w, vs.w, rtol=3e-16, atol=0)
+    np.testing.assert_allclose(w, vs.w, rtol=5e-16, atol=0)
     # opposites are exact negatives on the library side too
-    np.testing.assert_array_equal(c[18:], -c[:18])
+    P = vs.Q // 2
+    np.testing.assert_array_equal(c[P:], -c[:P])
+    Q, NN = ctypes.c_int(), ctypes.c_int()
+    assert B.lib().esbgk_tvd_set_info(B._GH_SET[name], ctypes.byref(Q), ctypes.byref(NN), None, None) == 0
+    assert (Q.value, NN.value) == (vs.Q, N)
+
+
+def test_tvd_set_info_rejects_other_sets():
+    from paper_1209_6548_amd import binding as B
+    for v in (0, B.D2Q37, B.D3Q39, 6):
+        assert B.lib().esbgk_tvd_set_info(v, None, None, None, None) == B.E_INVALID
 
 
 def test_tvd_workspace_bytes_validates_shapes():

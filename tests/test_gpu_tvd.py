@@ -19,7 +19,8 @@ from tests import helpers as H
 
 pytestmark = pytest.mark.gpu
 
-GH = OF.ProductSet(6, 2, 4)
+SETS = {"D2Q16GH": OF.ProductSet(4, 2, 3), "D2Q36GH": OF.ProductSet(6, 2, 4), "D2Q64GH": OF.ProductSet(8, 2, 4)}
+GH = SETS["D2Q36GH"]                     # the paper's set
 
 # (nx, ny): idle slots in every row, several wavefronts per row, a thin
 # periodic strip (x wraps inside every wavefront), one-cell rows (1-D in y)
@@ -35,7 +36,8 @@ def _fields(f, prob):
 WALLS = dict(T=(0.98, 1.04), u=(-0.04, 0.05))
 
 
-def _pair(dims, storage, cfl=0.5, Kn=0.005, Pr=2 / 3, g=(0.02, -0.01), seed=5, amp=0.02, walls=None):
+def _pair(dims, storage, cfl=0.5, Kn=0.005, Pr=2 / 3, g=(0.02, -0.01), seed=5, amp=0.02, walls=None,
+          velset="D2Q36GH"):
     """GPU lattice and oracle problem with the same seeded start; walls =
     dict(T=(T_lo, T_hi), u=(u_lo, u_hi)) puts diffuse walls on the first
     and last rows."""
@@ -47,15 +49,16 @@ def _pair(dims, storage, cfl=0.5, Kn=0.005, Pr=2 / 3, g=(0.02, -0.01), seed=5, a
     if walls:
         kw = dict(walls=True, wall_lo=OL.Wall(walls["T"][0], (walls["u"][0], 0.0, 0.0)),
                   wall_hi=OL.Wall(walls["T"][1], (walls["u"][1], 0.0, 0.0)))
-    prob = OF.TVDProblem(GH, dims, Kn=Kn, Pr=Pr, g=g + (0.0,), cfl=cfl, n_ref=n_ref, **kw)
-    lat = TVDLattice(dims[0], dims[1], storage=storage, cfl=cfl, n_ref=n_ref, walls=bool(walls))
+    vs = SETS[velset]
+    prob = OF.TVDProblem(vs, dims, Kn=Kn, Pr=Pr, g=g + (0.0,), cfl=cfl, n_ref=n_ref, **kw)
+    lat = TVDLattice(dims[0], dims[1], storage=storage, cfl=cfl, n_ref=n_ref, walls=bool(walls), velset=velset)
     assert lat.dt == pytest.approx(prob.dt, rel=1e-14)
     lat.set_gas(Kn, Pr)
     lat.set_body_force(g)
     if walls:
         for side in (0, 1):
             lat.set_wall(side, walls["T"][side], (walls["u"][side], 0.0, 0.0))
-    rho, u, T, xi, amp = H.init_fields(None, prob.M, 2, GH.Q, seed=seed, amp=amp)
+    rho, u, T, xi, amp = H.init_fields(None, prob.M, 2, vs.Q, seed=seed, amp=amp)
     lat.init_equilibrium(rho, u, T, xi, amp)
     f = OF.equilibrium_state(prob, rho, u.T, T, xi, amp)
     return lat, prob, f
@@ -120,6 +123,47 @@ def test_tvd_walls_wider_channel_fp32():
     lat.step(3)
     f = OF.run(f, prob, 3)
     H.assert_parity(lat.read_moments(), _fields(f, prob), "f32")
+
+
+@pytest.mark.parametrize("velset", ["D2Q16GH", "D2Q64GH"])
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_tvd_other_sets_parity(velset, walls, storage):
+    """The 4- and 8-point product sets (N = 3 and 4) through the same
+    kernels: 12 steps on a ragged 70 x 9 grid, periodic or walled."""
+    lat, prob, f = _pair((70, 9), storage, walls=WALLS if walls else None, velset=velset)
+    lat.step(12)
+    f = OF.run(f, prob, 12)
+    ea, er = H.assert_parity(lat.read_moments(), _fields(f, prob), storage)
+    print(velset, walls, storage, "scale", max(ea.values()), "signal", max(er.values()))
+    if storage == "f64":
+        h, ho = lat.get_populations(), f / prob.vs.w[:, None] - 1.0
+        assert np.abs(h - ho).max() / np.abs(ho).max() < 1e-12
+
+
+def test_tvd_velocity_set_study():
+    """The velocity-set convergence study on the GPU: Couette flow at
+    Kn = 0.5 to t = 10 with the 4-, 6- and 8-point sets in FP64. Each run
+    matches the oracle's, and the slip and shear stress change by less with
+    the richer set."""
+    slip, sxy = [], []
+    for velset in ("D2Q16GH", "D2Q36GH", "D2Q64GH"):
+        walls = dict(T=(1.0, 1.0), u=(-0.05, 0.05))
+        lat, prob, _ = _pair((1, 13), "f64", cfl=0.9, Kn=0.5, g=(0.0, 0.0), amp=0.0, walls=walls, velset=velset)
+        M = prob.M
+        lat.init_equilibrium()
+        f = OF.equilibrium_state(prob, np.ones(M), np.zeros((M, 2)), np.ones(M))
+        steps = int(round(10.0 / prob.dt))
+        lat.step(steps)
+        f = OF.run(f, prob, steps)
+        g = lat.read_moments()
+        H.assert_parity(g, _fields(f, prob), "f64")
+        slip.append(0.05 - g["u"][0][-1])
+        sxy.append(g["sigma"][1][1:-1].mean())
+        print(velset, steps, "slip", slip[-1], "sigma_xy", sxy[-1])
+    for seq in (slip, sxy):
+        d = np.abs(np.diff(seq))
+        assert d[1] < 0.7 * d[0], seq
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
