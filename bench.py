@@ -11,9 +11,12 @@ Printed: one JSON line with MLUPS (the metric), the roofline of the step
 kernel (algorithmic bytes 2 Q s per cell update / measured kernel time
 against the 8 TB/s HBM peak), the same workload with plain FP64 and with
 FP16 storage, the batched-channel workload in one persistent launch against
-a per-problem FP64 loop, 3-D workloads, the paper's own TVD scheme on the
-6-point Gauss-Hermite set (1024 x 1024, FP32 and FP64), and the FP64 CPU
-oracle timed on a bounded sample.
+a per-problem FP64 loop, the same channel at Pr = 1, the 1 x 32 Couette
+channel in FP64 (latency-bound), 3-D workloads (the 256^3 box in FP32,
+FP16 and FP64; the 512 x 512 x 256 FP16 channel), the paper's own TVD
+scheme on the 6-point Gauss-Hermite set (1024 x 1024, FP32 and FP64), and
+its 4- and 8-point sets (D2Q16, D2Q64) in FP32, and the FP64 CPU oracle
+timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--only-main]
 """
@@ -84,30 +87,55 @@ def bench_single(cfg, storage, steps, warmup):
 TVD_CFG = dict(name="periodic_gas_1024x1024_d2q36", dims=(1024, 1024), Kn=0.05, Pr=2 / 3, cfl=0.5)
 
 
-def bench_tvd(storage, steps, warmup):
-    """The paper's own scheme (forward Euler, TVD minmod fluxes) on the
-    6-point Gauss-Hermite product set D2Q36, 1024 x 1024 periodic cells,
-    from a perturbed equilibrium (the kernel's work does not depend on the
-    state: the limiter branches are selects)."""
+def bench_tvd(storage, steps, warmup, velset="D2Q36GH"):
+    """The paper's own scheme (forward Euler, TVD minmod fluxes) on a
+    Gauss-Hermite product set (the paper's D2Q36 by default), 1024 x 1024
+    periodic cells, from a perturbed equilibrium (the kernel's work does not
+    depend on the state: the limiter branches are selects)."""
     from paper_1209_6548_amd import TVDLattice
     nx, ny = TVD_CFG["dims"]
-    lat = TVDLattice(nx, ny, storage=storage, cfl=TVD_CFG["cfl"])
+    lat = TVDLattice(nx, ny, storage=storage, cfl=TVD_CFG["cfl"], velset=velset)
+    Q = lat.Q
     lat.set_gas(TVD_CFG["Kn"], TVD_CFG["Pr"])
     lat.set_body_force((1e-3, 0.0))
     rng = np.random.default_rng(1)
-    lat.init_equilibrium(noise=rng.standard_normal((36, nx * ny)), amplitude=1e-3)
+    lat.init_equilibrium(noise=rng.standard_normal((Q, nx * ny)), amplitude=1e-3)
     ms = time_steps(lat, steps, warmup)
     cells = nx * ny
     s = {"f64": 8, "f32": 4, "f16": 2}[storage]
     m = lat.read_moments()
-    traffic = measured_traffic(storage, TVD_TRAFFIC_FILE)
-    out = dict(workload=TVD_CFG["name"], storage=storage, ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6,
-               algorithmic_GBs=2 * 36 * s * cells / (ms * 1e-3) / 1e9, bytes_per_cell=2 * 36 * s,
-               kernel=f"k_tvd<{storage}>", traffic=traffic,
-               traffic_over_algorithmic=round(traffic / (2 * 36 * s * cells), 4) if traffic else None,
+    traffic = measured_traffic(storage, TVD_TRAFFIC_FILE) if velset == "D2Q36GH" else None
+    out = dict(workload=TVD_CFG["name"].replace("d2q36", velset.lower()), storage=storage, ms_per_step=ms,
+               mlups=cells / (ms * 1e-3) / 1e6, algorithmic_GBs=2 * Q * s * cells / (ms * 1e-3) / 1e9,
+               bytes_per_cell=2 * Q * s, kernel=f"k_tvd<{velset}, {storage}>", traffic=traffic,
+               traffic_over_algorithmic=round(traffic / (2 * Q * s * cells), 4) if traffic else None,
                finite=bool(np.isfinite(m["rho"]).all()))
     lat.close()
     return out
+
+
+def bench_couette_persistent(cfg, steps):
+    """The 1 x 32 Couette channel as a batch of one: all steps in one
+    persistent launch instead of one launch per step."""
+    import torch
+
+    from paper_1209_6548_amd import Batch, make_problem
+    p = make_problem(cfg["velset"], cfg["dims"][0], cfg["dims"][1], storage="f64", Kn=cfg["Kn"], Pr=cfg["Pr"],
+                     varpi=cfg["varpi"], T_w=cfg["T_w"], u_w=cfg["u_w"], g=cfg["g"])
+    b = Batch([p])
+    b.init_equilibrium()
+    b.step(100)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    cells = cfg["dims"][0] * cfg["dims"][1]
+    b.close()
+    return dict(steps=steps, ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6)
 
 
 def bench_batch(r, steps, warmup, fp64_sample=16):
@@ -303,15 +331,27 @@ def main():
         for st in ("f64", "f16"):
             variants[st] = bench_single(cfg, st, max(20, args.steps // 2), args.warmup)
             log(f"{st}: {variants[st]['mlups']:.0f} MLUPS, {variants[st]['algorithmic_GBs']:.0f} GB/s")
+        cfg1 = workloads.poiseuille_thermal_1024(r, Pr=1.0)
+        key = f"{cfg1['name']}_Pr1_f32"
+        variants[key] = bench_single(cfg1, "f32", max(20, args.steps // 2), args.warmup)
+        log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
+        c0 = workloads.couette_1x32(r)
+        variants["couette_1x32_f64"] = bench_single(c0, "f64", 2000, 100)
+        variants["couette_1x32_f64"]["regime"] = "latency-bound (32 cells): not an HBM-roofline regime"
+        variants["couette_1x32_f64"]["persistent"] = bench_couette_persistent(c0, 20000)
+        log(f"couette_1x32_f64: {variants['couette_1x32_f64']['mlups']:.1f} MLUPS in graphs, "
+            f"{variants['couette_1x32_f64']['persistent']['mlups']:.1f} MLUPS in one persistent launch")
         variants["batched_channels"] = bench_batch(r, max(50, args.steps), args.warmup)
+        variants["batched_channels"]["regime"] = ("cache-resident (about 160 MB of populations, inside the "
+                                                  "256 MB Infinity Cache): not an HBM-roofline regime")
         log(f"batch: {variants['batched_channels']['mlups']:.0f} MLUPS")
         r3 = lattice_info("D3Q39")["r"]
         # 3-D workloads (timed from the rest state: the step's work does not depend on it)
         box = dict(name="shear_wave_256^3", velset="D3Q39", dims=(256, 256, 256), walls=False, Kn=0.02,
                    Pr=2 / 3, varpi=0.5, g=(0.0, 0.0, 0.0))
-        for st in ("f32", "f16"):
+        for st in ("f32", "f16", "f64"):
             key = f"shear_wave_256^3_{st}"
-            variants[key] = bench_single(box, st, max(20, args.steps // 4), 5)
+            variants[key] = bench_single(box, st, max(10, args.steps // (4 if st != "f64" else 10)), 3)
             log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
         ch = workloads.channel_3d(r3)
         key = f"{ch['name']}_f16"
@@ -320,6 +360,10 @@ def main():
         for st in ("f32", "f64"):
             key = f"{TVD_CFG['name']}_{st}"
             variants[key] = bench_tvd(st, max(20, args.steps // 2), 5)
+            log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
+        for vs in ("D2Q16GH", "D2Q64GH"):          # the velocity-set study's other sets: cost grows with Q
+            key = f"{TVD_CFG['name'].replace('d2q36', vs.lower())}_f32"
+            variants[key] = bench_tvd("f32", max(20, args.steps // 2), 5, velset=vs)
             log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
     copy_gbs = None
     if not args.only_main:
