@@ -78,7 +78,9 @@ class ProductSet:
         for idx in product(range(n), repeat=D):
             if idx[0] >= half:                      # first component positive
                 reps.append(idx)
-        reps.sort(key=lambda t: (sum(xi[k] ** 2 for k in t), tuple(-k for k in t)))
+        # |c|^2 summed over the sorted squares, so that permuted tuples tie
+        # exactly and the root-index rule (not rounding) orders them
+        reps.sort(key=lambda t: (sum(sorted(xi[k] ** 2 for k in t)), tuple(-k for k in t)))
         opp = [tuple(n - 1 - k for k in t) for t in reps]   # xi[n-1-k] = -xi[k]
         order = reps + opp
         self.name = f"D{D}Q{n ** D}GH"
