@@ -61,7 +61,8 @@ enum {
 
 enum { ESBGK_D2Q37 = 1, ESBGK_D3Q39 = 2,             /* on-lattice velocity sets */
        ESBGK_D2Q36GH = 3,                            /* 6-point Gauss-Hermite product set (esbgk_tvd_*) */
-       ESBGK_D2Q16GH = 4, ESBGK_D2Q64GH = 5 };       /* 4- and 8-point product sets (esbgk_tvd_*) */
+       ESBGK_D2Q16GH = 4, ESBGK_D2Q64GH = 5,         /* 4- and 8-point product sets (esbgk_tvd_*) */
+       ESBGK_D3Q216GH = 6 };                         /* 3-D cube of the 6-point rule (esbgk_tvd_*) */
 enum { ESBGK_F64 = 0, ESBGK_F32 = 1, ESBGK_F16 = 2 };  /* storage of h; FP64 computes in FP64, the others in FP32 */
 enum { ESBGK_TRAPEZOID = 0, ESBGK_EULER = 1 };         /* time discretisation of eq. lbgk */
 
@@ -254,7 +255,9 @@ const char* esbgk_batch_last_error(const esbgk_batch* b);
  * degree 11 along each axis, carrying the N = 4 expansion). For
  * velocity-set convergence studies the 4-point (ESBGK_D2Q16GH: degree 7,
  * N = 3) and 8-point (ESBGK_D2Q64GH: degree 15, N = 4) products run the
- * same scheme. The abscissae lie
+ * same scheme; the paper's validation runs use D = 3, its set cubed
+ * (ESBGK_D3Q216GH: 216 velocities, exact to degree 11 per axis, N = 4). The
+ * abscissae lie
  * off the lattice, so streaming is the paper's finite-difference update:
  * forward Euler in time and, along each axis, the second-order TVD flux
  * difference with the minmod limiter,
@@ -266,22 +269,26 @@ const char* esbgk_batch_last_error(const esbgk_batch* b);
  * physical f (deviational h = f/w - 1 in the storage type, in the velocity
  * order of esbgk_tvd_set_info).
  *
- * Boundaries: periodic in x; in y periodic (walls = 0) or bounded by the
- * diffuse walls of Sec. 3.2 (walls = 1): rows 0 and ny - 1 lie on the
- * walls and are updated like every row, the ghost rows the stencil reaches
- * beyond a wall copy the wall row, and after each step the wall row's
- * populations moving into the gas become rho_W S(T_W, u_W) with rho_W the
- * normal flux toward the wall at the first row off it over that of S (a
- * second small kernel launch). Walls are fully diffuse at fixed T_W, u_W.
+ * Boundaries: periodic in every axis but the last (y in 2-D, z in 3-D);
+ * across the last axis periodic (walls = 0) or bounded by the diffuse walls
+ * of Sec. 3.2 (walls = 1): its first and last node rows (planes) lie on the
+ * walls and are updated like every node, the ghost nodes the stencil
+ * reaches beyond a wall copy the wall node, and after each step the wall
+ * node's populations moving into the gas become rho_W S(T_W, u_W) with
+ * rho_W the normal flux toward the wall at the first node off it over that
+ * of S (a second small kernel launch). Walls are fully diffuse at fixed
+ * T_W, u_W.
  *
- * Shape: velset = ESBGK_D2Q16GH / D2Q36GH / D2Q64GH, nz = 1, walls = 0 or 1 (ny >= 3),
+ * Shape: velset = ESBGK_D2Q16GH / D2Q36GH / D2Q64GH (nz = 1) or
+ * ESBGK_D3Q216GH, walls = 0 or 1 (three or more nodes across the channel),
  * scheme = ESBGK_EULER, storage F64 / F32 / F16 (FP32 compute for the last
- * two), n_ref = N_L (0: nx, or the wall distance ny - 1 with walls). The
+ * two), n_ref = N_L (0: nx, or the wall distance in nodes minus one with
+ * walls). The
  * time step is dt = cfl dx / max|c| with dx = 1/N_L and 0 < cfl <= 1; the
  * largest root, and so dt, depends on the set. */
 typedef struct esbgk_tvd esbgk_tvd;
 
-/* Number of velocities Q, Hermite order N, abscissae c[Q][2] and weights
+/* Number of velocities Q, Hermite order N, abscissae c[Q][D] and weights
  * w[Q] of a product set (any output may be NULL), derived on the host from
  * the roots of He_n and eq. weight; the velocities are ordered by |c|^2,
  * then by descending tuple of root indices, with the opposite of velocity
@@ -303,13 +310,14 @@ double esbgk_tvd_time_step(const esbgk_tvd* t);
 /* Gas (as esbgk_set_gas); E_UNSTABLE when forward Euler is unstable at
  * rho = T = 1 (dt/tau >= 2 or dt/(Pr tau) >= 2). */
 int esbgk_tvd_set_gas(esbgk_tvd* t, double Kn, double Pr, double varpi);
-/* Wall side (0: y = 0, 1: y = ny - 1) at temperature T_w > 0 moving with
- * u_w = (u_x, 0, 0) (NULL: at rest); defaults T_w = 1, at rest. E_INVALID
- * on a lattice without walls. */
+/* Wall side (0: the first node row of the last axis, 1: the last) at
+ * temperature T_w > 0 moving in its own plane with u_w (no component
+ * across the channel; NULL: at rest); defaults T_w = 1, at rest.
+ * E_INVALID on a lattice without walls. */
 int esbgk_tvd_set_wall(esbgk_tvd* t, int side, double T_w, const double u_w[3]);
 int esbgk_tvd_set_body_force(esbgk_tvd* t, const double g[3]);
 /* Initial state f = rho S(T, u) (1 + amplitude noise) as
- * esbgk_init_equilibrium (u is [2][cells], noise [Q][cells]). */
+ * esbgk_init_equilibrium (u is [D][cells], noise [Q][cells]). */
 int esbgk_tvd_init_equilibrium(esbgk_tvd* t, const double* rho, const double* u, const double* T,
                                const double* noise, double amplitude);
 /* Stored populations as FP64 h[Q][cells] (host); set rounds to the storage
@@ -318,8 +326,9 @@ int esbgk_tvd_set_populations(esbgk_tvd* t, const double* h);
 int esbgk_tvd_get_populations(esbgk_tvd* t, double* h);
 /* Advance n steps (asynchronous on the handle's stream). */
 int esbgk_tvd_step(esbgk_tvd* t, int64_t n);
-/* rho, u[2], T, sigma (xx, xy, yy), q[2] of the stored f per cell, as
- * [9][cells] FP64 (FP64 arithmetic); synchronises. */
+/* rho, u[D], T, sigma (i <= j: xx, xy, yy or xx, xy, xz, yy, yz, zz), q[D]
+ * of the stored f per cell, as [F][cells] FP64 (F = 9 in 2-D, 14 in 3-D;
+ * FP64 arithmetic); synchronises. */
 int esbgk_tvd_read_moments(esbgk_tvd* t, double* h_out, int* F);
 int64_t esbgk_tvd_steps_done(const esbgk_tvd* t);
 /* Text of the last error on the handle; with NULL, why the last create on

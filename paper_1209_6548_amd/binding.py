@@ -16,12 +16,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libesbgk.so")
 
 OK, E_INVALID, E_NOMEM, E_HIP, E_NONFINITE, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5, -6
-D2Q37, D3Q39, D2Q36GH, D2Q16GH, D2Q64GH = 1, 2, 3, 4, 5
+D2Q37, D3Q39, D2Q36GH, D2Q16GH, D2Q64GH, D3Q216GH = 1, 2, 3, 4, 5, 6
 F64, F32, F16 = 0, 1, 2
 TRAPEZOID, EULER = 0, 1
 
 _VELSET = {"D2Q37": D2Q37, "D3Q39": D3Q39}
-_GH_SET = {"D2Q16GH": D2Q16GH, "D2Q36GH": D2Q36GH, "D2Q64GH": D2Q64GH}
+_GH_SET = {"D2Q16GH": D2Q16GH, "D2Q36GH": D2Q36GH, "D2Q64GH": D2Q64GH, "D3Q216GH": D3Q216GH}
 _STORAGE = {"f64": F64, "f32": F32, "f16": F16}
 _SCHEME = {"trapezoid": TRAPEZOID, "euler": EULER}
 _NAMES = {E_INVALID: "E_INVALID", E_NOMEM: "E_NOMEM", E_HIP: "E_HIP", E_NONFINITE: "E_NONFINITE",
@@ -393,14 +393,15 @@ class Batch:
 
 
 def tvd_velocity_set(velset="D2Q36GH"):
-    """Abscissae c[Q][2] and weights w[Q] of a Gauss-Hermite product set of
-    the paper's own scheme (D2Q16GH, D2Q36GH: the paper's, D2Q64GH)."""
+    """Abscissae c[Q][D] and weights w[Q] of a Gauss-Hermite product set of
+    the paper's own scheme (D2Q16GH, D2Q36GH: the paper's, D2Q64GH, and the
+    paper's 3-D set D3Q216GH)."""
     Q, N = ctypes.c_int(), ctypes.c_int()
     vid = _GH_SET[velset]
     rc = lib().esbgk_tvd_set_info(vid, ctypes.byref(Q), ctypes.byref(N), None, None)
     if rc:
         raise EsbgkError(rc, "tvd_set_info")
-    c = np.empty((Q.value, 2))
+    c = np.empty((Q.value, 3 if velset == "D3Q216GH" else 2))
     w = np.empty(Q.value)
     rc = lib().esbgk_tvd_set_info(vid, None, None, _dp(c), _dp(w))
     if rc:
@@ -411,17 +412,17 @@ def tvd_velocity_set(velset="D2Q36GH"):
 class TVDLattice:
     """The paper's own scheme (forward Euler, TVD minmod fluxes) on a
     Gauss-Hermite product set (the paper's D2Q36GH by default; D2Q16GH and
-    D2Q64GH for velocity-set studies): periodic in x, and in y periodic or
-    (walls=True) bounded by diffuse walls on rows 0 and ny - 1."""
-
-    D = 2
+    D2Q64GH for velocity-set studies; the paper's 3-D set D3Q216GH with
+    nz): periodic in every axis but the last, which is periodic or
+    (walls=True) bounded by diffuse walls on its first and last nodes."""
 
     def __init__(self, nx=64, ny=64, storage="f32", cfl=0.5, n_ref=0, walls=False, velset="D2Q36GH",
-                 device="cuda:0"):
+                 device="cuda:0", nz=1):
         import torch
         self.device = torch.device(device)
-        self.dims = (nx, ny)
-        self.cells = nx * ny
+        self.D = 3 if velset == "D3Q216GH" else 2
+        self.dims = (nx, ny) if self.D == 2 else (nx, ny, nz)
+        self.cells = nx * ny * nz
         self.storage = storage
         self.walls = bool(walls)
         self.velset = velset
@@ -429,7 +430,7 @@ class TVDLattice:
         if lib().esbgk_tvd_set_info(_GH_SET[velset], ctypes.byref(Q), ctypes.byref(N), None, None):
             raise EsbgkError(E_INVALID, f"unknown set {velset}")
         self.Q, self.N = Q.value, N.value
-        self.shape = Shape(_GH_SET[velset], nx, ny, 1, int(self.walls), _STORAGE[storage], EULER, n_ref)
+        self.shape = Shape(_GH_SET[velset], nx, ny, nz, int(self.walls), _STORAGE[storage], EULER, n_ref)
         L = lib()
         nbytes = L.esbgk_tvd_workspace_bytes(ctypes.byref(self.shape))
         if nbytes == 0:
@@ -501,7 +502,7 @@ class TVDLattice:
         self._check(lib().esbgk_tvd_step(self._t, int(n)), "tvd_step")
 
     def read_moments(self):
-        out = np.empty((9, self.cells))
+        out = np.empty((9 if self.D == 2 else 14, self.cells))
         f = ctypes.c_int()
         self._check(lib().esbgk_tvd_read_moments(self._t, _dp(out), ctypes.byref(f)), "tvd_read_moments")
         return split_fields(out, self.D)

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libesbgk.so")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "batch.hip", "tvd.hip", "tables.cpp", "api.cpp", "batch_api.cpp", "tvd_api.cpp"]
+SOURCES = ["kernels.hip", "batch.hip", "tvd.hip", "tvd3.hip", "tables.cpp", "api.cpp", "batch_api.cpp", "tvd_api.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -263,13 +263,12 @@ __device__ __forceinline__ void collide_gh(C (&h)[L::Q], const GHConsts<C>* __re
 }
 
 // rho, u[2], T, sigma (xx, xy, yy), q[2] of the stored (physical) f.
+// rho, u[D], T, sigma (i <= j), q[D] from the raw moments of the stored
+// (physical) f.
 template <class L, typename C>
-__device__ __forceinline__ void cell_fields_gh(const C (&h)[L::Q], const GHConsts<C>* __restrict__ g,
-                                               const LatConsts<C>* __restrict__ lc,
-                                               const ProbParams<C>* __restrict__ pp, double* out) {
-  constexpr int D = 2;
-  RawMoments<L, C> m;
-  raw_moments_gh<L, C>(h, g, true, m);
+__device__ __forceinline__ void fields_from_moments(const RawMoments<L, C>& m, const LatConsts<C>* __restrict__ lc,
+                                                    const ProbParams<C>* __restrict__ pp, double* out) {
+  constexpr int D = L::D;
   CellState<L, C> s;
   reconstruct<L, C>(m, lc, pp, s);
   C A3[3][3][3], a2[3][3], a3[3][3][3];
@@ -294,6 +293,15 @@ __device__ __forceinline__ void cell_fields_gh(const C (&h)[L::Q], const GHConst
     for (int j = 0; j < D; ++j) { t3 += a3[i][j][j]; au += a2[i][j] * s.u[j]; }
     out[f++] = double(C(0.5) * (t3 - s.u[i] * tra2 - C(2) * au + C(2) * s.rho * s.u[i] * uu));
   }
+}
+
+template <class L, typename C>
+__device__ __forceinline__ void cell_fields_gh(const C (&h)[L::Q], const GHConsts<C>* __restrict__ g,
+                                               const LatConsts<C>* __restrict__ lc,
+                                               const ProbParams<C>* __restrict__ pp, double* out) {
+  RawMoments<L, C> m;
+  raw_moments_gh<L, C>(h, g, true, m);
+  fields_from_moments<L, C>(m, lc, pp, out);
 }
 
 // minmod(a, b): 0 unless a and b share a sign, else the one smaller in

@@ -23,7 +23,7 @@
 #include "lattice.h"
 #include "params.h"
 #include "tables.h"
-#include "gh.h"
+#include "gh3.h"
 
 namespace esbgk {
 
@@ -338,6 +338,36 @@ const HostGH* host_gh(int n) {
     ok[i] = n == 4 ? build_gh<D2Q16GH>(tabs[i]) : (n == 6 ? build_gh<D2Q36GH>(tabs[i]) : build_gh<D2Q64GH>(tabs[i]));
   });
   return ok[i] ? &tabs[i] : nullptr;
+}
+
+const HostGH3* host_gh3() {
+  static HostGH3 gh;
+  static bool ok = false;
+  static std::once_flag once;
+  std::call_once(once, [&]() {
+    using L = D3Q216GH;
+    std::vector<ld> x, w;
+    if (!gauss_hermite_rule(L::n, x, w)) return;
+    constexpr int H = L::H;
+    ld xi[H], w1[H];
+    for (int m = 0; m < H; ++m) {
+      xi[m] = 0.5L * (x[H + m] - x[H - 1 - m]);
+      w1[m] = 0.5L * (w[H + m] + w[H - 1 - m]);
+      gh.xi[m] = double(xi[m]);
+    }
+    for (int a = 0; a < L::Q; ++a) {
+      ld wa = 1;
+      for (int i = 0; i < 3; ++i) {
+        const int k = L::ranks.K[a % L::P][i] * (a < L::P ? 1 : -1);
+        const int m = (k < 0 ? -k : k) - 1;
+        gh.c[a][i] = double(k < 0 ? -xi[m] : xi[m]);
+        wa *= w1[m];
+      }
+      gh.w[a] = double(wa);
+    }
+    ok = true;
+  });
+  return ok ? &gh : nullptr;
 }
 
 // S(T, u)(c) / w - 1 at the velocity c[D]: eq. feq0 with rho = 1, truncated

@@ -32,6 +32,15 @@ struct HostGH {
 };
 const HostGH* host_gh(int n);
 
+// The 3-D cube of the 6-point rule, D3Q216: positive roots xi[0..2], and
+// per velocity (in the order of D3Q216GH) c[a][3] and w[a].
+struct HostGH3 {
+  double xi[3];
+  double c[216][3];
+  double w[216];
+};
+const HostGH3* host_gh3();
+
 // S(T, u)/w - 1 at velocity a (eq. feq0, rho = 1, order N of the lattice).
 double shat_minus_one(const HostLattice& lat, int a, double T, const double u[3]);
 // The same at an arbitrary velocity c[D], truncated at order N.

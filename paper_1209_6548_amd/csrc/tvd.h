@@ -48,4 +48,20 @@ hipError_t launch_tvd_init(int velset, int storage, const TVDArgs& a, const doub
                            uint32_t count);
 hipError_t launch_tvd_moments(int velset, int storage, const TVDArgs& a, uint32_t c0, uint32_t count, double* out);
 
+// The 3-D set D3Q216 (walls across z); as TVDWalls with 216 velocities.
+template <typename C>
+struct TVDWalls3 {
+  C kin[2][216];
+  C k0[2];
+  C sw[2][216];
+};
+
+hipError_t launch_tvd3_step(int storage, const TVDArgs& a);
+hipError_t launch_tvd3_walls(int storage, const TVDArgs& a, const void* walls);
+// c[216][3]; u is [3][count]; noise [216][count].
+hipError_t launch_tvd3_init(int storage, const TVDArgs& a, const double* c, const double* rho, const double* u,
+                            const double* T, const double* noise, double amp, uint32_t c0, uint32_t count);
+// writes [14][count]
+hipError_t launch_tvd3_moments(int storage, const TVDArgs& a, uint32_t c0, uint32_t count, double* out);
+
 }  // namespace esbgk

@@ -1,6 +1,7 @@
-// C ABI of the paper's own scheme (Sec. 3.1) on the 6-point Gauss-Hermite
-// product set: handle management, validation, workspace layout, parameter
-// upload, state I/O and the step loop.
+// C ABI of the paper's own scheme (Sec. 3.1) on the Gauss-Hermite product
+// sets (2-D: 4, 6 or 8 points per axis; 3-D: the paper's 6-point cube):
+// handle management, validation, workspace layout, parameter upload, state
+// I/O and the step loop.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -9,7 +10,7 @@
 #include <vector>
 
 #include "../../include/esbgk.h"
-#include "gh.h"
+#include "gh3.h"
 #include "tables.h"
 #include "tvd.h"
 
@@ -19,14 +20,44 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr uint32_t STAGE_CELLS = 65536;
-constexpr int QGH_MAX = 64;
 
-// Points of the 1-D rule of a product set (0: not a set of this scheme).
-int set_points(int velset) {
-  return velset == ESBGK_D2Q16GH ? 4 : (velset == ESBGK_D2Q36GH ? 6 : (velset == ESBGK_D2Q64GH ? 8 : 0));
+// The host view of a product set: dimension, sizes, abscissae c[Q][D],
+// weights and the largest root (max |c| along an axis).
+struct SetTab {
+  int velset = 0, D = 0, Q = 0, P = 0, N = 0;
+  double cmax = 0.0;
+  const double* c = nullptr;
+  const double* w = nullptr;
+};
+
+bool set_tab(int velset, SetTab& t) {
+  t.velset = velset;
+  if (velset == ESBGK_D3Q216GH) {
+    const HostGH3* g = host_gh3();
+    if (!g) return false;
+    t.D = 3;
+    t.Q = 216;
+    t.P = 108;
+    t.N = 4;
+    t.cmax = g->xi[2];
+    t.c = &g->c[0][0];
+    t.w = g->w;
+    return true;
+  }
+  const int n = velset == ESBGK_D2Q16GH ? 4 : (velset == ESBGK_D2Q36GH ? 6 : (velset == ESBGK_D2Q64GH ? 8 : 0));
+  const HostGH* g = n ? host_gh(n) : nullptr;
+  if (!g) return false;
+  t.D = 2;
+  t.Q = g->Q;
+  t.P = g->P;
+  t.N = g->N;
+  t.cmax = g->xi[n / 2 - 1];
+  t.c = &g->c[0][0];
+  t.w = g->w;
+  return true;
 }
-constexpr int NFIELDS = 9;
 
+int nfields(int D) { return D == 3 ? 14 : 9; }
 size_t align_up(size_t n) { return (n + ALIGN - 1) / ALIGN * ALIGN; }
 size_t ssize(int storage) { return storage == ESBGK_F64 ? 8 : (storage == ESBGK_F32 ? 4 : 2); }
 size_t csize(int storage) { return storage == ESBGK_F64 ? 8 : 4; }
@@ -38,79 +69,117 @@ struct TLayout {
 bool valid_tvd_shape(const esbgk_shape* s, Geometry* g, std::string* why) {
   auto fail = [&](const char* m) { if (why) *why = m; return false; };
   if (!s) return fail("null shape");
-  if (!set_points(s->velset)) return fail("velset must be ESBGK_D2Q16GH, ESBGK_D2Q36GH or ESBGK_D2Q64GH");
-  if (s->nx < 1 || s->ny < 1 || s->nz != 1) return fail("extents: nx, ny >= 1 and nz = 1");
-  if (s->walls != 0 && s->walls != 1) return fail("walls must be 0 (periodic) or 1 (walls across y)");
-  if (s->walls && s->ny < 3) return fail("a channel needs ny >= 3 (two wall rows and one between)");
+  SetTab t;
+  if (!set_tab(s->velset, t))
+    return fail("velset must be ESBGK_D2Q16GH, ESBGK_D2Q36GH, ESBGK_D2Q64GH or ESBGK_D3Q216GH");
+  if (s->nx < 1 || s->ny < 1 || s->nz < 1) return fail("extents must be >= 1");
+  if (t.D == 2 && s->nz != 1) return fail("a 2-D set needs nz = 1");
+  if (s->walls != 0 && s->walls != 1) return fail("walls must be 0 (periodic) or 1 (walls across the last axis)");
+  const int nwall = t.D == 2 ? s->ny : s->nz;
+  if (s->walls && nwall < 3) return fail("a channel needs three nodes across it (two wall nodes and one between)");
   if (s->storage < ESBGK_F64 || s->storage > ESBGK_F16) return fail("storage must be F64, F32 or F16");
   if (s->scheme != ESBGK_EULER) return fail("the paper's scheme is forward Euler (scheme = ESBGK_EULER)");
   if (s->n_ref < 0) return fail("n_ref must be >= 0");
-  const HostGH* gh = host_gh(set_points(s->velset));
-  if (!gh) return fail("velocity set tables unavailable");
   Geometry tmp;
-  if (!make_geometry(2, gh->Q, uint32_t(s->nx), uint32_t(s->ny), 1, s->walls != 0, true, ssize(s->storage),
-                     g ? *g : tmp))
-    return fail("lattice too large for the slice layout (one row of populations must be < 4 GiB)");
+  if (!make_geometry(t.D, t.Q, uint32_t(s->nx), uint32_t(s->ny), uint32_t(s->nz), s->walls != 0, true,
+                     ssize(s->storage), g ? *g : tmp))
+    return fail("lattice too large for the slice layout (one slice of populations must be < 4 GiB)");
   return true;
 }
 
+template <int D, typename C>
+using ConstsOf = typename std::conditional<D == 3, GH3Consts<C>, GHConsts<C>>::type;
+template <int D, typename C>
+using WallsOf = typename std::conditional<D == 3, TVDWalls3<C>, TVDWalls<C>>::type;
+
 TLayout tlayout(const esbgk_shape* s, const Geometry& g) {
+  SetTab t;
+  set_tab(s->velset, t);
   TLayout L{};
   const size_t ss = ssize(s->storage), cs = csize(s->storage);
-  const size_t cells = size_t(s->nx) * s->ny;
+  const size_t cells = size_t(s->nx) * s->ny * s->nz;
+  const bool d3 = t.D == 3;
+  const size_t gc64 = d3 ? sizeof(ConstsOf<3, double>) : sizeof(ConstsOf<2, double>);
+  const size_t gc32 = d3 ? sizeof(ConstsOf<3, float>) : sizeof(ConstsOf<2, float>);
+  const size_t w64 = d3 ? sizeof(WallsOf<3, double>) : sizeof(WallsOf<2, double>);
+  const size_t w32 = d3 ? sizeof(WallsOf<3, float>) : sizeof(WallsOf<2, float>);
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
   L.pop[0] = take(size_t(g.nslices) * g.sstride * ss);
   L.pop[1] = take(size_t(g.nslices) * g.sstride * ss);
-  L.gc = take(cs == 8 ? sizeof(GHConsts<double>) : sizeof(GHConsts<float>));
+  L.gc = take(cs == 8 ? gc64 : gc32);
   L.lc = take(cs == 8 ? sizeof(LatConsts<double>) : sizeof(LatConsts<float>));
   L.pp = take(cs == 8 ? sizeof(ProbParams<double>) : sizeof(ProbParams<float>));
-  L.gc64 = cs == 8 ? L.gc : take(sizeof(GHConsts<double>));
+  L.gc64 = cs == 8 ? L.gc : take(gc64);
   L.lc64 = cs == 8 ? L.lc : take(sizeof(LatConsts<double>));
   L.pp64 = cs == 8 ? L.pp : take(sizeof(ProbParams<double>));
-  L.walls = take(cs == 8 ? sizeof(TVDWalls<double>) : sizeof(TVDWalls<float>));
-  L.c = take(sizeof(double) * QGH_MAX * 2);
+  L.walls = take(cs == 8 ? w64 : w32);
+  L.c = take(sizeof(double) * size_t(t.Q) * t.D);
   const size_t stage = std::min<size_t>(cells, STAGE_CELLS);
-  L.staging = take(stage * size_t(std::max(NFIELDS, 4 + QGH_MAX)) * sizeof(double));
+  // init stages rho, u[D], T and noise[Q]; the read-out stages the fields
+  L.staging = take(stage * size_t(std::max(nfields(t.D), 2 + t.D + t.Q)) * sizeof(double));
   L.total = off;
   return L;
 }
 
+// Per-set constants of the kernels: weights, monomials, Courant numbers.
 template <typename C>
-void pack_gh(const HostGH& gh, double nu_scale, GHConsts<C>& d) {
+void pack_consts(const SetTab& t, double nu_scale, GHConsts<C>& d) {
   std::memset(&d, 0, sizeof(d));
-  for (int p = 0; p < gh.P; ++p) {
-    const double x = gh.c[p][0], y = gh.c[p][1];
+  for (int p = 0; p < t.P; ++p) {
+    const double x = t.c[2 * p], y = t.c[2 * p + 1];
     const double m[GH_MONO] = {x,         y,         x * x,         x * y,         y * y,
                                x * x * x, x * x * y, x * y * y,     y * y * y,     x * x * x * x,
                                x * x * x * y, x * x * y * y, x * y * y * y, y * y * y * y};
-    d.w[p] = C(gh.w[p]);
+    d.w[p] = C(t.w[p]);
     for (int k = 0; k < GH_MONO; ++k) d.mono[p][k] = C(m[k]);
-    const double nx = x * nu_scale, ny = y * nu_scale;
-    d.nu[p][0] = C(nx);
-    d.nu[p][1] = C(ny);
-    d.nk[p][0] = C(0.5 * std::fabs(nx) * (1.0 - std::fabs(nx)));
-    d.nk[p][1] = C(0.5 * std::fabs(ny) * (1.0 - std::fabs(ny)));
+    for (int i = 0; i < 2; ++i) {
+      const double nu = t.c[2 * p + i] * nu_scale;
+      d.nu[p][i] = C(nu);
+      d.nk[p][i] = C(0.5 * std::fabs(nu) * (1.0 - std::fabs(nu)));
+    }
   }
 }
 
-// Wall tables of Sec. 3.2 (see TVDWalls) from the walls' T and u.
 template <typename C>
-void pack_walls(const HostGH& gh, const double Tw[2], const double uw[2][3], TVDWalls<C>& d) {
+void pack_consts(const SetTab& t, double nu_scale, GH3Consts<C>& d) {
   std::memset(&d, 0, sizeof(d));
+  for (int p = 0; p < t.P; ++p) {
+    const double* cp = t.c + 3 * p;
+    d.w[p] = C(t.w[p]);
+    for (int k = 0; k < GH3_MONO; ++k) {
+      double v = 1.0;
+      for (int j = 0; j < MONO3.deg[k]; ++j) v *= cp[MONO3.idx[k][j]];
+      d.mono[p][k] = C(v);
+    }
+    for (int i = 0; i < 3; ++i) {
+      const double nu = cp[i] * nu_scale;
+      d.nu[p][i] = C(nu);
+      d.nk[p][i] = C(0.5 * std::fabs(nu) * (1.0 - std::fabs(nu)));
+    }
+  }
+}
+
+// Wall tables of Sec. 3.2 (see TVDWalls) from the walls' T and u; the walls
+// lie across the last axis.
+template <class W>
+void pack_walls(const SetTab& t, const double Tw[2], const double uw[2][3], W& d) {
+  using C = typename std::remove_reference<decltype(d.k0[0])>::type;
+  std::memset(&d, 0, sizeof(d));
+  std::vector<double> sw(size_t(t.Q));
   for (int side = 0; side < 2; ++side) {
-    const double nrm = side == 0 ? 1.0 : -1.0;   // inward normal along y
-    double den = 0.0, sw[QGH_MAX];
-    for (int a = 0; a < gh.Q; ++a) {
-      sw[a] = 1.0 + shat_minus_one_at(2, gh.N, gh.c[a], Tw[side], uw[side]);
-      const double cn = nrm * gh.c[a][1];
-      if (cn > 0) den += cn * gh.w[a] * sw[a];
+    const double nrm = side == 0 ? 1.0 : -1.0;   // inward normal along the last axis
+    double den = 0.0;
+    for (int a = 0; a < t.Q; ++a) {
+      sw[a] = 1.0 + shat_minus_one_at(t.D, t.N, t.c + size_t(a) * t.D, Tw[side], uw[side]);
+      const double cn = nrm * t.c[size_t(a) * t.D + t.D - 1];
+      if (cn > 0) den += cn * t.w[a] * sw[a];
     }
     double k0 = 0.0;
-    for (int a = 0; a < gh.Q; ++a) {
-      const double cn = nrm * gh.c[a][1];
+    for (int a = 0; a < t.Q; ++a) {
+      const double cn = nrm * t.c[size_t(a) * t.D + t.D - 1];
       if (cn < 0) {
-        const double k = -cn * gh.w[a] / den;
+        const double k = -cn * t.w[a] / den;
         d.kin[side][a] = C(k);
         k0 += k;
       } else {
@@ -136,7 +205,7 @@ struct esbgk_tvd {
   std::string err;
   double Kn = 0.1, Pr = 1.0, varpi = 0.5, cfl = 0.5, dt = 0.0, dx = 0.0;
   double g[3] = {0, 0, 0};
-  const HostGH* gh = nullptr;   // the velocity set's host tables
+  SetTab set;                   // the velocity set's host tables
   double Tw[2] = {1.0, 1.0};
   double uw[2][3] = {{0, 0, 0}, {0, 0, 0}};
   char* at(size_t off) const { return ws + off; }
@@ -185,9 +254,11 @@ TVDArgs targs(const esbgk_tvd* c) {
   return a;
 }
 
+template <int D>
+int upload_consts(esbgk_tvd* c, double nu_scale);
+
 // Gas, force and the Courant-limited time step: dt = CFL dx / max|c|.
 int upload_tvd(esbgk_tvd* c) {
-  const HostGH& gh = *c->gh;
   HostProblem hp{};
   hp.dt = c->dt;
   hp.hs = 0.0;
@@ -198,45 +269,56 @@ int upload_tvd(esbgk_tvd* c) {
   hp.b = 1.0 - 1.0 / c->Pr;
   hp.force = 0;
   for (int i = 0; i < 3; ++i) {
-    hp.g[i] = i < 2 ? c->g[i] : 0.0;
+    hp.g[i] = i < c->set.D ? c->g[i] : 0.0;
     if (hp.g[i] != 0.0) hp.force = 1;
   }
   hp.gam[0] = hp.gam[1] = 1.0;
   const double nu_scale = c->dt / c->dx;
   static thread_local ProbParams<double> pp64;
   static thread_local ProbParams<float> pp32;
-  static thread_local GHConsts<double> g64;
-  static thread_local GHConsts<float> g32;
   static thread_local LatConsts<double> l64;
   static thread_local LatConsts<float> l32;
   pack_params<double>(hp, 0, pp64);   // the wall tables of ProbParams are not used here
-  pack_gh<double>(gh, nu_scale, g64);
   std::memset(&l64, 0, sizeof(l64));
-  l64.r = 1.0;                        // the weights live in GHConsts
+  l64.r = 1.0;                        // the weights live in the set constants
   TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.pp64), &pp64, sizeof(pp64), hipMemcpyHostToDevice, c->stream), "upload");
-  TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.gc64), &g64, sizeof(g64), hipMemcpyHostToDevice, c->stream), "upload");
   TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.lc64), &l64, sizeof(l64), hipMemcpyHostToDevice, c->stream), "upload");
   if (!c->f64()) {
     pack_params<float>(hp, 0, pp32);
-    pack_gh<float>(gh, nu_scale, g32);
     std::memset(&l32, 0, sizeof(l32));
     l32.r = 1.0f;
     TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.pp), &pp32, sizeof(pp32), hipMemcpyHostToDevice, c->stream), "upload");
-    TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.gc), &g32, sizeof(g32), hipMemcpyHostToDevice, c->stream), "upload");
     TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.lc), &l32, sizeof(l32), hipMemcpyHostToDevice, c->stream), "upload");
   }
+  const int rc = c->set.D == 3 ? upload_consts<3>(c, c->dt / c->dx) : upload_consts<2>(c, c->dt / c->dx);
+  if (rc) return rc;
+  TVD_HIP(c, hipStreamSynchronize(c->stream), "upload");
+  return ESBGK_OK;
+}
+
+// The set constants (FP64 always, the compute type too) and the wall
+// tables; the host copies stay alive until the synchronisation above.
+template <int D>
+int upload_consts(esbgk_tvd* c, double nu_scale) {
+  static thread_local ConstsOf<D, double> g64;
+  static thread_local ConstsOf<D, float> g32;
+  static thread_local WallsOf<D, double> w64;
+  static thread_local WallsOf<D, float> w32;
+  pack_consts<double>(c->set, nu_scale, g64);
+  TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.gc64), &g64, sizeof(g64), hipMemcpyHostToDevice, c->stream), "upload");
+  if (!c->f64()) {
+    pack_consts<float>(c->set, nu_scale, g32);
+    TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.gc), &g32, sizeof(g32), hipMemcpyHostToDevice, c->stream), "upload");
+  }
   if (c->shape.walls) {
-    static thread_local TVDWalls<double> w64;
-    static thread_local TVDWalls<float> w32;
     if (c->f64()) {
-      pack_walls<double>(gh, c->Tw, c->uw, w64);
+      pack_walls(c->set, c->Tw, c->uw, w64);
       TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.walls), &w64, sizeof(w64), hipMemcpyHostToDevice, c->stream), "upload");
     } else {
-      pack_walls<float>(gh, c->Tw, c->uw, w32);
+      pack_walls(c->set, c->Tw, c->uw, w32);
       TVD_HIP(c, hipMemcpyAsync(c->at(c->lay.walls), &w32, sizeof(w32), hipMemcpyHostToDevice, c->stream), "upload");
     }
   }
-  TVD_HIP(c, hipStreamSynchronize(c->stream), "upload");
   return ESBGK_OK;
 }
 
@@ -272,18 +354,12 @@ hipError_t tplane_to_host(esbgk_tvd* c, int q, void* host) {
 extern "C" {
 
 int esbgk_tvd_set_info(int velset, int* Q, int* N, double* c, double* w) {
-  const int n = set_points(velset);
-  const HostGH* gh = n ? host_gh(n) : nullptr;
-  if (!gh) return ESBGK_E_INVALID;
-  if (Q) *Q = gh->Q;
-  if (N) *N = gh->N;
-  for (int a = 0; a < gh->Q; ++a) {
-    if (c) {
-      c[2 * a] = gh->c[a][0];
-      c[2 * a + 1] = gh->c[a][1];
-    }
-    if (w) w[a] = gh->w[a];
-  }
+  SetTab t;
+  if (!set_tab(velset, t)) return ESBGK_E_INVALID;
+  if (Q) *Q = t.Q;
+  if (N) *N = t.N;
+  if (c) std::memcpy(c, t.c, sizeof(double) * size_t(t.Q) * t.D);
+  if (w) std::memcpy(w, t.w, sizeof(double) * size_t(t.Q));
   return ESBGK_OK;
 }
 
@@ -321,17 +397,13 @@ int esbgk_tvd_create(const esbgk_shape* shape, double cfl, void* d_workspace, si
   c->ws = static_cast<char*>(d_workspace);
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->cfl = cfl;
-  const int n_ref = shape->n_ref > 0 ? shape->n_ref : (shape->walls ? shape->ny - 1 : shape->nx);
+  set_tab(shape->velset, c->set);
+  const int nwall = c->set.D == 2 ? shape->ny : shape->nz;
+  const int n_ref = shape->n_ref > 0 ? shape->n_ref : (shape->walls ? nwall - 1 : shape->nx);
   c->dx = 1.0 / double(n_ref);
-  c->gh = host_gh(set_points(shape->velset));
-  const HostGH& gh = *c->gh;
-  c->dt = cfl * c->dx / gh.xi[gh.n / 2 - 1];
-  double cc[QGH_MAX * 2] = {};
-  for (int a = 0; a < gh.Q; ++a) {
-    cc[2 * a] = gh.c[a][0];
-    cc[2 * a + 1] = gh.c[a][1];
-  }
-  hipError_t e = hipMemcpyAsync(c->at(lay.c), cc, sizeof(cc), hipMemcpyHostToDevice, c->stream);
+  c->dt = cfl * c->dx / c->set.cmax;
+  hipError_t e = hipMemcpyAsync(c->at(lay.c), c->set.c, sizeof(double) * size_t(c->set.Q) * c->set.D,
+                                hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     g_tvd_create_error = std::string("create: ") + hipGetErrorString(e);
@@ -375,12 +447,14 @@ int esbgk_tvd_set_wall(esbgk_tvd* c, int side, double T_w, const double u_w[3]) 
   if (side != 0 && side != 1) return tset_err(c, ESBGK_E_INVALID, "side must be 0 or 1");
   if (!(T_w > 0.0) || !std::isfinite(T_w)) return tset_err(c, ESBGK_E_INVALID, "T_w must be > 0");
   double u[3] = {0, 0, 0};
+  const int D = c->set.D;
   if (u_w)
     for (int i = 0; i < 3; ++i) {
       if (!std::isfinite(u_w[i])) return tset_err(c, ESBGK_E_INVALID, "u_w must be finite");
-      u[i] = i < 2 ? u_w[i] : 0.0;
+      u[i] = i < D ? u_w[i] : 0.0;
     }
-  if (u[1] != 0.0) return tset_err(c, ESBGK_E_INVALID, "a wall moves in its own plane (u_w[1] = 0)");
+  if (u[D - 1] != 0.0)
+    return tset_err(c, ESBGK_E_INVALID, "a wall moves in its own plane (no component across the channel)");
   c->Tw[side] = T_w;
   for (int i = 0; i < 3; ++i) c->uw[side][i] = u[i];
   return upload_tvd(c);
@@ -391,7 +465,7 @@ int esbgk_tvd_set_body_force(esbgk_tvd* c, const double g[3]) {
   if (!g) return tset_err(c, ESBGK_E_INVALID, "g is null");
   for (int i = 0; i < 3; ++i) {
     if (!std::isfinite(g[i])) return tset_err(c, ESBGK_E_INVALID, "g must be finite");
-    c->g[i] = i < 2 ? g[i] : 0.0;
+    c->g[i] = i < c->set.D ? g[i] : 0.0;
   }
   return upload_tvd(c);
 }
@@ -407,22 +481,28 @@ int esbgk_tvd_init_equilibrium(esbgk_tvd* c, const double* rho, const double* u,
   double* st = reinterpret_cast<double*>(c->at(c->lay.staging));
   for (uint32_t c0 = 0; c0 < cells; c0 += STAGE_CELLS) {
     const uint32_t n = std::min(STAGE_CELLS, cells - c0);
+    const int D = c->set.D;
     double* d_rho = st;
     double* d_u = d_rho + n;
-    double* d_T = d_u + 2 * size_t(n);
+    double* d_T = d_u + size_t(D) * n;
     double* d_noise = d_T + n;
     if (rho) TVD_HIP(c, hipMemcpyAsync(d_rho, rho + c0, n * 8, hipMemcpyHostToDevice, c->stream), "stage");
     if (u)
-      for (int d = 0; d < 2; ++d)
+      for (int d = 0; d < D; ++d)
         TVD_HIP(c, hipMemcpyAsync(d_u + size_t(d) * n, u + size_t(d) * cells + c0, n * 8, hipMemcpyHostToDevice,
                                   c->stream), "stage");
     if (T) TVD_HIP(c, hipMemcpyAsync(d_T, T + c0, n * 8, hipMemcpyHostToDevice, c->stream), "stage");
     if (noise)
-      for (int q = 0; q < c->gh->Q; ++q)
+      for (int q = 0; q < c->set.Q; ++q)
         TVD_HIP(c, hipMemcpyAsync(d_noise + size_t(q) * n, noise + size_t(q) * cells + c0, n * 8,
                                   hipMemcpyHostToDevice, c->stream), "stage");
-    TVD_HIP(c, launch_tvd_init(c->shape.velset, c->shape.storage, a, dc, rho ? d_rho : nullptr, u ? d_u : nullptr,
-                               T ? d_T : nullptr, noise ? d_noise : nullptr, amplitude, c0, n), "init");
+    if (D == 3)
+      TVD_HIP(c, launch_tvd3_init(c->shape.storage, a, dc, rho ? d_rho : nullptr, u ? d_u : nullptr,
+                                  T ? d_T : nullptr, noise ? d_noise : nullptr, amplitude, c0, n), "init");
+    else
+      TVD_HIP(c, launch_tvd_init(c->shape.velset, c->shape.storage, a, dc, rho ? d_rho : nullptr,
+                                 u ? d_u : nullptr, T ? d_T : nullptr, noise ? d_noise : nullptr, amplitude, c0, n),
+              "init");
     TVD_HIP(c, hipStreamSynchronize(c->stream), "init");
   }
   c->state_set = true;
@@ -435,7 +515,7 @@ int esbgk_tvd_set_populations(esbgk_tvd* c, const double* h) {
   if (!h) return tset_err(c, ESBGK_E_INVALID, "h is null");
   const size_t cells = c->geo.ncells;
   std::vector<unsigned char> buf;
-  for (int q = 0; q < c->gh->Q; ++q) {
+  for (int q = 0; q < c->set.Q; ++q) {
     const double* src = h + size_t(q) * cells;
     const void* p = src;
     if (c->shape.storage == ESBGK_F32) {
@@ -460,7 +540,7 @@ int esbgk_tvd_get_populations(esbgk_tvd* c, double* h) {
   const size_t cells = c->geo.ncells, ss = ssize(c->shape.storage);
   std::vector<unsigned char> buf(cells * ss);
   TVD_HIP(c, hipStreamSynchronize(c->stream), "get populations");
-  for (int q = 0; q < c->gh->Q; ++q) {
+  for (int q = 0; q < c->set.Q; ++q) {
     TVD_HIP(c, tplane_to_host(c, q, buf.data()), "get populations");
     TVD_HIP(c, hipStreamSynchronize(c->stream), "get populations");
     double* o = h + size_t(q) * cells;
@@ -477,9 +557,14 @@ int esbgk_tvd_step(esbgk_tvd* c, int64_t n) {
   if (!c->state_set) return tset_err(c, ESBGK_E_STATE, "no state set");
   for (int64_t k = 0; k < n; ++k) {
     const TVDArgs a = targs(c);
-    TVD_HIP(c, launch_tvd_step(c->shape.velset, c->shape.storage, a), "step");
-    if (c->shape.walls)
-      TVD_HIP(c, launch_tvd_walls(c->shape.velset, c->shape.storage, a, c->at(c->lay.walls)), "walls");
+    if (c->set.D == 3) {
+      TVD_HIP(c, launch_tvd3_step(c->shape.storage, a), "step");
+      if (c->shape.walls) TVD_HIP(c, launch_tvd3_walls(c->shape.storage, a, c->at(c->lay.walls)), "walls");
+    } else {
+      TVD_HIP(c, launch_tvd_step(c->shape.velset, c->shape.storage, a), "step");
+      if (c->shape.walls)
+        TVD_HIP(c, launch_tvd_walls(c->shape.velset, c->shape.storage, a, c->at(c->lay.walls)), "walls");
+    }
     c->cur ^= 1;
     c->steps += 1;
   }
@@ -490,18 +575,22 @@ int esbgk_tvd_read_moments(esbgk_tvd* c, double* h_out, int* F) {
   TVD_CHECK(c);
   if (!h_out) return tset_err(c, ESBGK_E_INVALID, "h_out is null");
   if (!c->state_set) return tset_err(c, ESBGK_E_STATE, "no state set");
-  if (F) *F = NFIELDS;
+  const int NF = nfields(c->set.D);
+  if (F) *F = NF;
   const uint32_t cells = c->geo.ncells;
   double* st = reinterpret_cast<double*>(c->at(c->lay.staging));
   std::vector<double> tmp;
   const TVDArgs a = targs(c);
   for (uint32_t c0 = 0; c0 < cells; c0 += STAGE_CELLS) {
     const uint32_t n = std::min(STAGE_CELLS, cells - c0);
-    TVD_HIP(c, launch_tvd_moments(c->shape.velset, c->shape.storage, a, c0, n, st), "moments");
-    tmp.resize(size_t(NFIELDS) * n);
+    if (c->set.D == 3)
+      TVD_HIP(c, launch_tvd3_moments(c->shape.storage, a, c0, n, st), "moments");
+    else
+      TVD_HIP(c, launch_tvd_moments(c->shape.velset, c->shape.storage, a, c0, n, st), "moments");
+    tmp.resize(size_t(NF) * n);
     TVD_HIP(c, hipMemcpyAsync(tmp.data(), st, tmp.size() * 8, hipMemcpyDeviceToHost, c->stream), "moments");
     TVD_HIP(c, hipStreamSynchronize(c->stream), "moments");
-    for (int f = 0; f < NFIELDS; ++f)
+    for (int f = 0; f < NF; ++f)
       std::memcpy(h_out + size_t(f) * cells + c0, tmp.data() + size_t(f) * n, n * 8);
   }
   return ESBGK_OK;

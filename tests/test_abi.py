@@ -90,13 +90,14 @@ def test_fast_division_constants():
             assert q == n // d, (d, n)
 
 
-@pytest.mark.parametrize("name,n,N", [("D2Q16GH", 4, 3), ("D2Q36GH", 6, 4), ("D2Q64GH", 8, 4)])
-def test_tvd_set_equals_the_oracle_product_set(name, n, N):
+@pytest.mark.parametrize("name,n,D,N", [("D2Q16GH", 4, 2, 3), ("D2Q36GH", 6, 2, 4), ("D2Q64GH", 8, 2, 4),
+                                        ("D3Q216GH", 6, 3, 4)])
+def test_tvd_set_equals_the_oracle_product_set(name, n, D, N):
     from oracle import offlattice
     from paper_1209_6548_amd import binding as B
     from paper_1209_6548_amd import tvd_velocity_set
     c, w = tvd_velocity_set(name)
-    vs = offlattice.ProductSet(n, 2, N)
+    vs = offlattice.ProductSet(n, D, N)
     # same order; both sides round the 50-digit (oracle) or long-double
     # (library) roots
     np.testing.assert_array_equal(c, vs.c)
@@ -111,7 +112,7 @@ def test_tvd_set_equals_the_oracle_product_set(name, n, N):
 
 def test_tvd_set_info_rejects_other_sets():
     from paper_1209_6548_amd import binding as B
-    for v in (0, B.D2Q37, B.D3Q39, 6):
+    for v in (0, B.D2Q37, B.D3Q39, 7):
         assert B.lib().esbgk_tvd_set_info(v, None, None, None, None) == B.E_INVALID
 
 
