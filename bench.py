@@ -15,8 +15,8 @@ a per-problem FP64 loop, the same channel at Pr = 1, the 1 x 32 Couette
 channel in FP64 (latency-bound), 3-D workloads (the 256^3 box in FP32,
 FP16 and FP64; the 512 x 512 x 256 FP16 channel), the paper's own TVD
 scheme on the 6-point Gauss-Hermite set (1024 x 1024, FP32 and FP64), and
-its 4- and 8-point sets (D2Q16, D2Q64) in FP32, and the FP64 CPU oracle
-timed on a bounded sample.
+its 4- and 8-point sets (D2Q16, D2Q64) in FP32, its 3-D set D3Q216 on a
+64^3 box in FP32, and the FP64 CPU oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--only-main]
 """
@@ -87,25 +87,31 @@ def bench_single(cfg, storage, steps, warmup):
 TVD_CFG = dict(name="periodic_gas_1024x1024_d2q36", dims=(1024, 1024), Kn=0.05, Pr=2 / 3, cfl=0.5)
 
 
-def bench_tvd(storage, steps, warmup, velset="D2Q36GH"):
+def bench_tvd(storage, steps, warmup, velset="D2Q36GH", dims=None):
     """The paper's own scheme (forward Euler, TVD minmod fluxes) on a
     Gauss-Hermite product set (the paper's D2Q36 by default), 1024 x 1024
-    periodic cells, from a perturbed equilibrium (the kernel's work does not
-    depend on the state: the limiter branches are selects)."""
+    periodic cells (or dims, 3-D for D3Q216GH), from a perturbed equilibrium
+    (the kernel's work does not depend on the state: the limiter branches
+    are selects)."""
     from paper_1209_6548_amd import TVDLattice
-    nx, ny = TVD_CFG["dims"]
-    lat = TVDLattice(nx, ny, storage=storage, cfl=TVD_CFG["cfl"], velset=velset)
+    dims = tuple(dims or TVD_CFG["dims"])
+    nx, ny = dims[0], dims[1]
+    nz = dims[2] if len(dims) > 2 else 1
+    lat = TVDLattice(nx, ny, nz=nz, storage=storage, cfl=TVD_CFG["cfl"], velset=velset)
     Q = lat.Q
     lat.set_gas(TVD_CFG["Kn"], TVD_CFG["Pr"])
-    lat.set_body_force((1e-3, 0.0))
+    lat.set_body_force((1e-3, 0.0, 0.0))
     rng = np.random.default_rng(1)
-    lat.init_equilibrium(noise=rng.standard_normal((Q, nx * ny)), amplitude=1e-3)
+    lat.init_equilibrium(noise=rng.standard_normal((Q, nx * ny * nz)), amplitude=1e-3)
     ms = time_steps(lat, steps, warmup)
-    cells = nx * ny
+    cells = nx * ny * nz
     s = {"f64": 8, "f32": 4, "f16": 2}[storage]
     m = lat.read_moments()
     traffic = measured_traffic(storage, TVD_TRAFFIC_FILE) if velset == "D2Q36GH" else None
-    out = dict(workload=TVD_CFG["name"].replace("d2q36", velset.lower()), storage=storage, ms_per_step=ms,
+    name = TVD_CFG["name"].replace("d2q36", velset.lower())
+    if dims != tuple(TVD_CFG["dims"]):
+        name = f"periodic_gas_{'x'.join(map(str, dims))}_{velset.lower()}"
+    out = dict(workload=name, storage=storage, ms_per_step=ms,
                mlups=cells / (ms * 1e-3) / 1e6, algorithmic_GBs=2 * Q * s * cells / (ms * 1e-3) / 1e9,
                bytes_per_cell=2 * Q * s, kernel=f"k_tvd<{velset}, {storage}>", traffic=traffic,
                traffic_over_algorithmic=round(traffic / (2 * Q * s * cells), 4) if traffic else None,
@@ -365,6 +371,9 @@ def main():
             key = f"{TVD_CFG['name'].replace('d2q36', vs.lower())}_f32"
             variants[key] = bench_tvd("f32", max(20, args.steps // 2), 5, velset=vs)
             log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
+        key = "periodic_gas_64x64x64_d3q216gh_f32"      # the paper's 3-D set
+        variants[key] = bench_tvd("f32", max(10, args.steps // 10), 3, velset="D3Q216GH", dims=(64, 64, 64))
+        log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
     copy_gbs = None
     if not args.only_main:
         copy_gbs = copy_bandwidth()
