@@ -16,7 +16,7 @@ channel in FP64 (latency-bound), 3-D workloads (the 256^3 box in FP32,
 FP16 and FP64; the 512 x 512 x 256 FP16 channel), the paper's own TVD
 scheme on the 6-point Gauss-Hermite set (1024 x 1024, FP32 and FP64), and
 its 4- and 8-point sets (D2Q16, D2Q64) in FP32, its 3-D set D3Q216 on a
-64^3 box in FP32, and the FP64 CPU oracle timed on a bounded sample.
+128^3 box in FP32, and the FP64 CPU oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--only-main]
 """
@@ -371,8 +371,8 @@ def main():
             key = f"{TVD_CFG['name'].replace('d2q36', vs.lower())}_f32"
             variants[key] = bench_tvd("f32", max(20, args.steps // 2), 5, velset=vs)
             log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
-        key = "periodic_gas_64x64x64_d3q216gh_f32"      # the paper's 3-D set
-        variants[key] = bench_tvd("f32", max(10, args.steps // 10), 3, velset="D3Q216GH", dims=(64, 64, 64))
+        key = "periodic_gas_128x128x128_d3q216gh_f32"   # the paper's 3-D set
+        variants[key] = bench_tvd("f32", max(5, args.steps // 20), 2, velset="D3Q216GH", dims=(128, 128, 128))
         log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
     copy_gbs = None
     if not args.only_main:

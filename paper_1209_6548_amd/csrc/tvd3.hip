@@ -41,8 +41,12 @@ __device__ __forceinline__ uint32_t xcd_block3(uint32_t b, uint32_t nb) {
 
 }  // namespace
 
+// Six waves per SIMD for FP32 compute (80 VGPRs, some spilled to scratch):
+// the pair loop is latency-bound, and on grids with more wavefronts than
+// slots the extra waves hide more of it (128^3: 24 % faster than the 114
+// VGPRs of the unbounded build) than the scratch reloads cost.
 template <typename S>
-__global__ void __launch_bounds__(BLOCK3)
+__global__ void __launch_bounds__(BLOCK3, (sizeof(S) == 8 ? 1 : 6))
 k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
        const GH3Consts<typename StepT3<S>::type>* __restrict__ gc,
        const LatConsts<typename StepT3<S>::type>* __restrict__ lc,
