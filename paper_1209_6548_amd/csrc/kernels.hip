@@ -39,17 +39,6 @@ constexpr int BLOCK = 256;
 // Compute type of the step for a storage type (FP32 for FP32/FP16 storage);
 // it is also the type of the wall partial sums and of the parameter blocks the
 // step reads.
-template <typename S> struct StepT { using type = float; };
-template <> struct StepT<double> { using type = double; };
-
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2). Give each XCD a contiguous range of tiles so that neighbouring tiles,
-// which share cache lines at their edges, are served by the same L2.
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
-  const uint32_t per = nb >> 3;
-  if (b < (per << 3)) return (b & 7u) * per + (b >> 3);
-  return b;
-}
 
 // ---- FP64 reductions ---------------------------------------------------------
 

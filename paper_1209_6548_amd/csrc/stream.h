@@ -23,6 +23,26 @@ namespace esbgk {
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv d) { return (__umulhi(n, d.m) + n) >> d.l; }
 
+// Compute type of a storage type: FP64 storage computes in FP64, FP32 and
+// FP16 storage in FP32.
+template <typename S>
+struct StepT {
+  using type = float;
+};
+template <>
+struct StepT<double> {
+  using type = double;
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2). Give each XCD a contiguous range of tiles so that neighbouring tiles,
+// which share cache lines at their edges, are served by the same L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t per = nb >> 3;
+  if (b < (per << 3)) return (b & 7u) * per + (b >> 3);
+  return b;
+}
+
 __device__ __forceinline__ int wrapc(int v, int n) {
   // v in [-3, n + 2], n >= 1
   if (v < 0) v += n;

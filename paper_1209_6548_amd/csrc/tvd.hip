@@ -22,21 +22,6 @@ namespace {
 
 constexpr uint32_t BLOCK = 256;
 
-template <typename S>
-struct StepT2 {
-  using type = float;
-};
-template <>
-struct StepT2<double> {
-  using type = double;
-};
-
-__device__ __forceinline__ uint32_t xcd_block2(uint32_t b, uint32_t nb) {
-  const uint32_t per = nb >> 3;
-  if (b < (per << 3)) return (b & 7u) * per + (b >> 3);
-  return b;
-}
-
 }  // namespace
 
 // Value of lane i - 1 (shr) or i + 1 (shl) of the wavefront; the lane
@@ -110,13 +95,13 @@ __device__ __forceinline__ void tvd_cell(const C (&h)[L::Q], const GHCollision<C
 template <class L, typename S>
 __global__ void __launch_bounds__(BLOCK)
 k_tvd(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
-      const GHConsts<typename StepT2<S>::type>* __restrict__ gc,
-      const LatConsts<typename StepT2<S>::type>* __restrict__ lc,
-      const ProbParams<typename StepT2<S>::type>* __restrict__ pp) {
-  using C = typename StepT2<S>::type;
+      const GHConsts<typename StepT<S>::type>* __restrict__ gc,
+      const LatConsts<typename StepT<S>::type>* __restrict__ lc,
+      const ProbParams<typename StepT<S>::type>* __restrict__ pp) {
+  using C = typename StepT<S>::type;
   constexpr int Q = L::Q;
   constexpr uint32_t ss = sizeof(S);
-  const uint32_t blk = xcd_block2(blockIdx.x, gridDim.x);
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t wave0 = blk * BLOCK + (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u);
   const uint32_t s = __builtin_amdgcn_readfirstlane(fdiv(wave0, geo.div_ipad));
   if (s >= geo.nslices) return;
@@ -161,8 +146,8 @@ k_tvd(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
 // populations moving into the gas.
 template <class L, typename S>
 __global__ void __launch_bounds__(BLOCK)
-k_tvd_walls(Geometry geo, S* __restrict__ pop, const TVDWalls<typename StepT2<S>::type>* __restrict__ w) {
-  using C = typename StepT2<S>::type;
+k_tvd_walls(Geometry geo, S* __restrict__ pop, const TVDWalls<typename StepT<S>::type>* __restrict__ w) {
+  using C = typename StepT<S>::type;
   const uint32_t x = blockIdx.x * BLOCK + threadIdx.x;
   const int side = int(blockIdx.y);
   if (x >= geo.inner) return;
@@ -249,7 +234,7 @@ k_tvd_moments(Geometry geo, const S* __restrict__ src, const GHConsts<double>* _
 
 template <class L, typename S>
 static hipError_t tvd_step_t(const TVDArgs& a) {
-  using C = typename StepT2<S>::type;
+  using C = typename StepT<S>::type;
   const uint32_t nb = uint32_t((uint64_t(a.geo.nslices) * a.geo.ipad + BLOCK - 1) / BLOCK);
   hipLaunchKernelGGL((k_tvd<L, S>), dim3(nb), dim3(BLOCK), 0, a.stream, a.geo, static_cast<const S*>(a.src),
                      static_cast<S*>(a.dst), static_cast<const GHConsts<C>*>(a.gc),
@@ -259,7 +244,7 @@ static hipError_t tvd_step_t(const TVDArgs& a) {
 
 template <class L, typename S>
 static hipError_t tvd_walls_t(const TVDArgs& a, const void* walls) {
-  using C = typename StepT2<S>::type;
+  using C = typename StepT<S>::type;
   const dim3 grid((a.geo.inner + BLOCK - 1) / BLOCK, 2);
   hipLaunchKernelGGL((k_tvd_walls<L, S>), grid, dim3(BLOCK), 0, a.stream, a.geo, static_cast<S*>(a.dst),
                      static_cast<const TVDWalls<C>*>(walls));

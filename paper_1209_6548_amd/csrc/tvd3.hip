@@ -24,21 +24,6 @@ namespace {
 
 constexpr uint32_t BLOCK3 = 256;
 
-template <typename S>
-struct StepT3 {
-  using type = float;
-};
-template <>
-struct StepT3<double> {
-  using type = double;
-};
-
-__device__ __forceinline__ uint32_t xcd_block3(uint32_t b, uint32_t nb) {
-  const uint32_t per = nb >> 3;
-  if (b < (per << 3)) return (b & 7u) * per + (b >> 3);
-  return b;
-}
-
 }  // namespace
 
 // Six waves per SIMD for FP32 compute (80 VGPRs, some spilled to scratch):
@@ -48,14 +33,14 @@ __device__ __forceinline__ uint32_t xcd_block3(uint32_t b, uint32_t nb) {
 template <typename S>
 __global__ void __launch_bounds__(BLOCK3, (sizeof(S) == 8 ? 1 : 6))
 k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
-       const GH3Consts<typename StepT3<S>::type>* __restrict__ gc,
-       const LatConsts<typename StepT3<S>::type>* __restrict__ lc,
-       const ProbParams<typename StepT3<S>::type>* __restrict__ pp) {
-  using C = typename StepT3<S>::type;
+       const GH3Consts<typename StepT<S>::type>* __restrict__ gc,
+       const LatConsts<typename StepT<S>::type>* __restrict__ lc,
+       const ProbParams<typename StepT<S>::type>* __restrict__ pp) {
+  using C = typename StepT<S>::type;
   using L = D3Q216GH;
   constexpr int P = L::P;
   constexpr uint32_t ss = sizeof(S);
-  const uint32_t blk = xcd_block3(blockIdx.x, gridDim.x);
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t wave0 = blk * BLOCK3 + (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u);
   const uint32_t s = __builtin_amdgcn_readfirstlane(fdiv(wave0, geo.div_ipad));
   if (s >= geo.nslices) return;
@@ -143,8 +128,8 @@ k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
 // i and wall side = blockIdx.y (see k_tvd_walls).
 template <typename S>
 __global__ void __launch_bounds__(BLOCK3)
-k_tvd3_walls(Geometry geo, S* __restrict__ pop, const TVDWalls3<typename StepT3<S>::type>* __restrict__ w) {
-  using C = typename StepT3<S>::type;
+k_tvd3_walls(Geometry geo, S* __restrict__ pop, const TVDWalls3<typename StepT<S>::type>* __restrict__ w) {
+  using C = typename StepT<S>::type;
   using L = D3Q216GH;
   const uint32_t i = blockIdx.x * BLOCK3 + threadIdx.x;
   const int side = int(blockIdx.y);
@@ -235,7 +220,7 @@ k_tvd3_moments(Geometry geo, const S* __restrict__ src, const GH3Consts<double>*
 
 template <typename S>
 static hipError_t tvd3_step_t(const TVDArgs& a) {
-  using C = typename StepT3<S>::type;
+  using C = typename StepT<S>::type;
   const uint32_t nb = uint32_t((uint64_t(a.geo.nslices) * a.geo.ipad + BLOCK3 - 1) / BLOCK3);
   hipLaunchKernelGGL(k_tvd3<S>, dim3(nb), dim3(BLOCK3), 0, a.stream, a.geo, static_cast<const S*>(a.src),
                      static_cast<S*>(a.dst), static_cast<const GH3Consts<C>*>(a.gc),
@@ -245,7 +230,7 @@ static hipError_t tvd3_step_t(const TVDArgs& a) {
 
 template <typename S>
 static hipError_t tvd3_walls_t(const TVDArgs& a, const void* walls) {
-  using C = typename StepT3<S>::type;
+  using C = typename StepT<S>::type;
   const dim3 grid((a.geo.inner + BLOCK3 - 1) / BLOCK3, 2);
   hipLaunchKernelGGL(k_tvd3_walls<S>, grid, dim3(BLOCK3), 0, a.stream, a.geo, static_cast<S*>(a.dst),
                      static_cast<const TVDWalls3<C>*>(walls));
