@@ -312,6 +312,18 @@ __device__ __forceinline__ double minmod(double a, double b) {
   return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
 }
 
+// Cache policy of the TVD kernels' population stores: non-temporal (2) when
+// a cell's Q populations take 144 bytes or more, else the default (0). The
+// stencil re-reads of the neighbouring rows are served by L2, and keeping the
+// stores out of it leaves more room for them. Measured on MI355X at 1024^2
+// (and 128^3 for D3Q216): 1-5 % faster for D2Q36 FP32, D2Q64 FP32, D2Q36
+// FP64 and D3Q216 FP32; 3 % slower for D2Q36 FP16 (72 B) and 17 % slower for
+// D2Q16 FP32 (64 B).
+template <typename S>
+constexpr int tvd_store_policy(int Q) {
+  return Q * int(sizeof(S)) >= 144 ? 2 : 0;
+}
+
 // The flux difference nu (F_{i+1/2} - F_{i-1/2}) of one velocity along one
 // axis (Sec. 3.1) is nu d + nk m, with nk = |nu| (1 - |nu|) / 2, d the
 // upwind difference (f_i - f_{i-1} for nu > 0, f_{i+1} - f_i for nu < 0)

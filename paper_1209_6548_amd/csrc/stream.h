@@ -145,8 +145,9 @@ __device__ __forceinline__ Rsrc block_rsrc(const void* base, uint32_t bytes) {
 }
 
 // Load / store one storage element at byte voff (per lane) + soff (uniform)
-// of a slice block. FP64 populations are stored non-temporally (measured
-// faster for FP64 on MI355X; slower for the narrower types).
+// of a slice block. POL is the store's cache policy: 2 (non-temporal) or 0.
+// The default stores FP64 populations non-temporally (the step kernel:
+// measured faster for FP64 on MI355X, slower for the narrower types).
 template <typename S>
 __device__ __forceinline__ S buf_ld(Rsrc r, uint32_t voff, uint32_t soff) {
   if constexpr (sizeof(S) == 8) {
@@ -158,15 +159,15 @@ __device__ __forceinline__ S buf_ld(Rsrc r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, int(voff), int(soff), 0));
   }
 }
-template <typename S>
+template <typename S, int POL = (sizeof(S) == 8 ? 2 : 0)>
 __device__ __forceinline__ void buf_st(S v, Rsrc r, uint32_t voff, uint32_t soff) {
   if constexpr (sizeof(S) == 8) {
     typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, int(voff), int(soff), 2);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, int(voff), int(soff), POL);
   } else if constexpr (sizeof(S) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, int(voff), int(soff), 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, int(voff), int(soff), POL);
   } else {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, int(voff), int(soff), 0);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, int(voff), int(soff), POL);
   }
 }
 

@@ -86,7 +86,7 @@ __device__ __forceinline__ void tvd_cell(const C (&h)[L::Q], const GHCollision<C
         t = fmac(sg * gc->nu[p][1], dy, t);
         t = fmac(gc->nk[p][0], mx, t);
         t = fmac(gc->nk[p][1], my, t);
-        buf_st<S>(narrow<S, C>(hs[side] - t), out, so, po);
+        buf_st<S, tvd_store_policy<S>(L::Q)>(narrow<S, C>(hs[side] - t), out, so, po);
       }
     }
   }

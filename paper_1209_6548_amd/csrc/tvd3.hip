@@ -119,7 +119,7 @@ k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
         t = fmac(nu, d, t);
         t = fmac(gc->nk[p][ax], m, t);
       }
-      buf_st<S>(narrow<S, C>(hs[side] - t), out, so, po);
+      buf_st<S, tvd_store_policy<S>(L::Q)>(narrow<S, C>(hs[side] - t), out, so, po);
     }
   }
 }
