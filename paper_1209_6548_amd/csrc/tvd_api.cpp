@@ -258,7 +258,15 @@ template <int D>
 int upload_consts(esbgk_tvd* c, double nu_scale);
 
 // Gas, force and the Courant-limited time step: dt = CFL dx / max|c|.
+// Waits for the stream when it leaves scope, also on an early error return:
+// the uploads read thread-local host blocks that the next call refills.
+struct StreamIdleOnExit {
+  hipStream_t s;
+  ~StreamIdleOnExit() { (void)hipStreamSynchronize(s); }
+};
+
 int upload_tvd(esbgk_tvd* c) {
+  const StreamIdleOnExit idle{c->stream};
   HostProblem hp{};
   hp.dt = c->dt;
   hp.hs = 0.0;
@@ -273,7 +281,6 @@ int upload_tvd(esbgk_tvd* c) {
     if (hp.g[i] != 0.0) hp.force = 1;
   }
   hp.gam[0] = hp.gam[1] = 1.0;
-  const double nu_scale = c->dt / c->dx;
   static thread_local ProbParams<double> pp64;
   static thread_local ProbParams<float> pp32;
   static thread_local LatConsts<double> l64;
