@@ -2,8 +2,9 @@
 //
 // The host packs the problems into bins of roughly equal cell count (longest
 // problem first, each into the currently lightest bin); one workgroup owns one
-// bin for the whole launch. Within a step every thread takes cells of the bin
-// in turn (cell -> problem through a prefix table in LDS), pulls, collides
+// bin for the whole launch. Within a step every wavefront takes 64 slots of
+// the bin in turn (slots -> problem through a prefix table in LDS, problems
+// starting on multiples of 64 slots), and each lane pulls, collides
 // and stores exactly as the single-lattice kernel does, with the problem's
 // own geometry and parameter block; a workgroup barrier separates steps, so
 // the bin advances n steps in one launch with no host round trip. The
@@ -48,33 +49,38 @@ k_batch(const BatchProblem* __restrict__ probs, const ProbParams<C>* __restrict_
   __shared__ uint32_t pid[BATCH_MAX_PER_BIN];
   const uint32_t p0 = bin_first[blockIdx.x], p1 = bin_first[blockIdx.x + 1];
   const uint32_t np = p1 - p0;
+  // slots of the bin: each problem's cells start on a multiple of 64, so that
+  // every wavefront's 64 slots lie in one problem, whose descriptor and
+  // parameter block the wavefront then reads as scalars
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
     for (uint32_t k = 0; k < np; ++k) {
       const uint32_t id = order[p0 + k];
       pid[k] = id;
       cum[k] = acc;
-      acc += probs[id].geo.ncells;
+      acc += (probs[id].geo.ncells + 63u) & ~63u;
     }
     cum[np] = acc;
   }
   __syncthreads();
   const uint32_t total = cum[np];
+  const uint32_t lane = threadIdx.x & 63u;
   for (int64_t s = 0; s < nsteps; ++s) {
     const bool odd = ((s + parity) & 1) != 0;
     const S* src = odd ? bufB : bufA;
     S* dst = odd ? bufA : bufB;
     const C* wps = odd ? wpB : wpA;
     C* wpd = odd ? wpA : wpB;
-    for (uint32_t t = threadIdx.x; t < total; t += blockDim.x) {
-      uint32_t k = 0, hi = np;   // cum[k] <= t < cum[k + 1]
+    for (uint32_t t0 = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u); t0 < total; t0 += blockDim.x) {
+      uint32_t k = 0, hi = np;   // cum[k] <= t0 < cum[k + 1]
       while (hi - k > 1) {
         const uint32_t mid = (k + hi) >> 1;
-        if (cum[mid] <= t) k = mid;
+        if (__builtin_amdgcn_readfirstlane(cum[mid]) <= t0) k = mid;
         else hi = mid;
       }
-      const uint32_t id = pid[k];
-      batch_cell<L, S, C>(probs[id], t - cum[k], src, dst, wps, wpd, lc, pps + id);
+      const uint32_t id = __builtin_amdgcn_readfirstlane(pid[k]);
+      const uint32_t cell = t0 - __builtin_amdgcn_readfirstlane(cum[k]) + lane;
+      if (cell < probs[id].geo.ncells) batch_cell<L, S, C>(probs[id], cell, src, dst, wps, wpd, lc, pps + id);
     }
     __syncthreads();
   }

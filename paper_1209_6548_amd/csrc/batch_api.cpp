@@ -129,7 +129,8 @@ int bfail(esbgk_batch* b, hipError_t e, const char* where) {
     if (_e != hipSuccess) return bfail(b, _e, where);     \
   } while (0)
 
-// Longest problem first, each into the bin with the fewest cells.
+// Longest problem first, each into the bin with the fewest cells (counted as
+// the kernel's slots: each problem rounded up to a multiple of 64).
 int build_bins(esbgk_batch* b, uint32_t nbins) {
   const int n = int(b->p.size());
   nbins = std::max<uint32_t>(1, std::min<uint32_t>(nbins, uint32_t(n)));
@@ -152,7 +153,7 @@ int build_bins(esbgk_batch* b, uint32_t nbins) {
       heap.pop();
     }
     bins[it.second].push_back(uint32_t(i));
-    it.first += b->bp[i].geo.ncells;
+    it.first += (b->bp[i].geo.ncells + 63u) & ~63u;
     heap.push(it);
   }
   std::vector<uint32_t> first(nbins + 1), order;
