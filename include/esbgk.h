@@ -235,8 +235,8 @@ int esbgk_batch_step(esbgk_batch* b, int64_t n);
 int esbgk_batch_read_moments(esbgk_batch* b, int i, double* h_out, int* F);
 /* Stored populations of problem i as FP64 h[Q][cells_i]; synchronises. */
 int esbgk_batch_get_populations(esbgk_batch* b, int i, double* h);
-/* Launch layout: workgroup size (multiple of 64, at most 1024 for F32, 512
- * for F16, 256 for F64 storage) and number of bins (one workgroup each;
+/* Launch layout: workgroup size (multiple of 64, at most 1024 for F32 and
+ * F16, 256 for F64 storage) and number of bins (one workgroup each;
  * problems are packed longest first into the lightest bin). The default is
  * the largest workgroup and one bin per resident workgroup. */
 int esbgk_batch_set_layout(esbgk_batch* b, int threads, int nbins);

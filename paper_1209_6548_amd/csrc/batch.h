@@ -9,10 +9,10 @@
 namespace esbgk {
 
 // Largest workgroup of the persistent kernel, chosen so that the kernel needs
-// no scratch: FP32 storage fits 1024 threads (at most 128 VGPRs), FP16 storage
-// 512, FP64 256.
+// no scratch: FP32 and FP16 storage fit 1024 threads (at most 128 VGPRs),
+// FP64 256.
 constexpr int batch_max_threads(size_t storage_bytes) {
-  return storage_bytes == 8 ? 256 : (storage_bytes == 4 ? 1024 : 512);
+  return storage_bytes == 8 ? 256 : 1024;
 }
 constexpr int BATCH_MAX_PER_BIN = 64;
 
