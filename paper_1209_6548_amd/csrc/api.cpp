@@ -17,7 +17,6 @@ using namespace esbgk;
 namespace {
 
 constexpr size_t ALIGN = 256;
-constexpr uint32_t BLOCK = 256;
 constexpr uint32_t STAGE_CELLS = 65536;   // cells per staged host transfer
 
 size_t align_up(size_t n) { return (n + ALIGN - 1) / ALIGN * ALIGN; }
@@ -68,7 +67,6 @@ Geometry geometry_of(const esbgk_shape* s) {
   return g;
 }
 
-uint32_t slot_blocks(const Geometry& g) { return uint32_t((uint64_t(g.nslices) * g.ipad + BLOCK - 1) / BLOCK); }
 
 Layout layout_of(const esbgk_shape* s) {
   const HostLattice* lat = host_lattice(s->velset);

@@ -30,6 +30,9 @@ struct StepArgs {
   hipStream_t stream;
 };
 
+// Workgroups of the step and reduction kernels (one FP64 partial each in
+// red_part).
+uint32_t slot_blocks(const Geometry& g);
 hipError_t launch_step(int velset, int storage, const StepArgs& a);
 hipError_t launch_reduce(int velset, int storage, const StepArgs& a);
 hipError_t launch_reduce_finalize(const double* part, uint32_t nparts, double* out, hipStream_t stream);
