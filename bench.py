@@ -347,7 +347,9 @@ def main():
         variants["couette_1x32_f64"]["persistent"] = bench_couette_persistent(c0, 20000)
         log(f"couette_1x32_f64: {variants['couette_1x32_f64']['mlups']:.1f} MLUPS in graphs, "
             f"{variants['couette_1x32_f64']['persistent']['mlups']:.1f} MLUPS in one persistent launch")
-        variants["batched_channels"] = bench_batch(r, max(50, args.steps), args.warmup)
+        # a persistent launch of ~30 us steps: time at least 1000 of them, so that the window is
+        # long against the clock ramp after the nearly idle 1 x 32 channel run
+        variants["batched_channels"] = bench_batch(r, max(1000, 5 * args.steps), max(100, args.warmup))
         variants["batched_channels"]["regime"] = ("cache-resident (about 160 MB of populations, inside the "
                                                   "256 MB Infinity Cache): not an HBM-roofline regime")
         log(f"batch: {variants['batched_channels']['mlups']:.0f} MLUPS")
