@@ -36,10 +36,6 @@ namespace esbgk {
 
 constexpr int BLOCK = 256;
 
-// Compute type of the step for a storage type (FP32 for FP32/FP16 storage);
-// it is also the type of the wall partial sums and of the parameter blocks the
-// step reads.
-
 // ---- FP64 reductions ---------------------------------------------------------
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -321,7 +317,6 @@ __global__ void __launch_bounds__(BLOCK)
 k_wall_partials(Geometry geo, const S* __restrict__ src, const LatConsts<typename StepT<S>::type>* __restrict__ lc,
                 typename StepT<S>::type* __restrict__ wp_dst) {
   using P = typename StepT<S>::type;
-  constexpr int D = L::D;
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= 6u * geo.ncols) return;
   const uint32_t col = i % geo.ncols;

@@ -151,7 +151,6 @@ __device__ __forceinline__ Rsrc block_rsrc(const void* base, uint32_t bytes) {
 template <typename S>
 __device__ __forceinline__ S buf_ld(Rsrc r, uint32_t voff, uint32_t soff) {
   if constexpr (sizeof(S) == 8) {
-    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
     return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), 0));
   } else if constexpr (sizeof(S) == 4) {
     return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0));
