@@ -285,7 +285,9 @@ const char* esbgk_batch_last_error(const esbgk_batch* b);
  * two), n_ref = N_L (0: nx, or the wall distance in nodes minus one with
  * walls). The
  * time step is dt = cfl dx / max|c| with dx = 1/N_L and 0 < cfl <= 1; the
- * largest root, and so dt, depends on the set. */
+ * largest root, and so dt, depends on the set. The axes' fluxes are summed
+ * unsplit: a field that varies along d axes needs cfl <= 1/d (every abscissa
+ * of these sets is nonzero), which is the caller's choice. */
 typedef struct esbgk_tvd esbgk_tvd;
 
 /* Number of velocities Q, Hermite order N, abscissae c[Q][D] and weights

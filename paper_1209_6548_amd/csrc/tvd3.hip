@@ -23,6 +23,7 @@ namespace esbgk {
 namespace {
 
 constexpr uint32_t BLOCK3 = 256;
+constexpr uint32_t Z3 = BLOCK3 / 64;   // slices per workgroup of the step kernel
 
 }  // namespace
 
@@ -40,11 +41,16 @@ k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
   using L = D3Q216GH;
   constexpr int P = L::P;
   constexpr uint32_t ss = sizeof(S);
+  // a workgroup takes one 64-cell chunk of the slice in Z3 consecutive
+  // slices (one wavefront each), chunks fastest: its wavefronts read each
+  // other's populations as z-neighbours at about the same velocity pair,
+  // and the y-neighbours are chunks started at about the same time
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t wave0 = blk * BLOCK3 + (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u);
-  const uint32_t s = __builtin_amdgcn_readfirstlane(fdiv(wave0, geo.div_ipad));
+  const uint32_t nchunks = geo.ipad >> 6;
+  const uint32_t band = blk / nchunks, chunk = blk - band * nchunks;
+  const uint32_t s = band * Z3 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (s >= geo.nslices) return;
-  const uint32_t i0 = __builtin_amdgcn_readfirstlane(wave0 - s * geo.ipad);
+  const uint32_t i0 = chunk * 64u;
   if (i0 >= geo.inner) return;                       // the slice's padding slots
   const uint32_t lane = threadIdx.x & 63u;
   // lanes past the end of the slice compute its last cell again and store
@@ -221,7 +227,7 @@ k_tvd3_moments(Geometry geo, const S* __restrict__ src, const GH3Consts<double>*
 template <typename S>
 static hipError_t tvd3_step_t(const TVDArgs& a) {
   using C = typename StepT<S>::type;
-  const uint32_t nb = uint32_t((uint64_t(a.geo.nslices) * a.geo.ipad + BLOCK3 - 1) / BLOCK3);
+  const uint32_t nb = (a.geo.ipad >> 6) * ((a.geo.nslices + Z3 - 1) / Z3);
   hipLaunchKernelGGL(k_tvd3<S>, dim3(nb), dim3(BLOCK3), 0, a.stream, a.geo, static_cast<const S*>(a.src),
                      static_cast<S*>(a.dst), static_cast<const GH3Consts<C>*>(a.gc),
                      static_cast<const LatConsts<C>*>(a.lc), static_cast<const ProbParams<C>*>(a.pp));

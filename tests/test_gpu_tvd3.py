@@ -28,7 +28,7 @@ def _fields(f, prob):
     return {"rho": rho, "u": u.T.copy(), "T": T, "sigma": sig, "q": q.T.copy()}
 
 
-def _pair(dims, storage, walls=None, Kn=0.02, g=(0.02, -0.01, 0.005), seed=13, amp=0.02, cfl=0.5):
+def _pair(dims, storage, walls=None, Kn=0.02, g=(0.02, -0.01, 0.005), seed=13, amp=0.02, cfl=0.3):
     from paper_1209_6548_amd import TVDLattice
     n_ref = max(dims)
     kw = {}
