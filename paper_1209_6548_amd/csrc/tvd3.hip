@@ -22,7 +22,7 @@ namespace esbgk {
 
 namespace {
 
-constexpr uint32_t BLOCK3 = 256;
+constexpr uint32_t BLOCK3 = 512;
 constexpr uint32_t Z3 = BLOCK3 / 64;   // slices per workgroup of the step kernel
 
 }  // namespace
@@ -41,10 +41,12 @@ k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
   using L = D3Q216GH;
   constexpr int P = L::P;
   constexpr uint32_t ss = sizeof(S);
-  // a workgroup takes one 64-cell chunk of the slice in Z3 consecutive
+  // a workgroup takes one 64-cell chunk of the slice in Z3 = 8 consecutive
   // slices (one wavefront each), chunks fastest: its wavefronts read each
   // other's populations as z-neighbours at about the same velocity pair,
-  // and the y-neighbours are chunks started at about the same time
+  // and the y-neighbours are chunks started at about the same time (measured
+  // at 128^3 FP32: 2.63 ms against 2.68 for 4 slices and 2.76 for 4 chunks
+  // of one slice)
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t nchunks = geo.ipad >> 6;
   const uint32_t band = blk / nchunks, chunk = blk - band * nchunks;
