@@ -27,12 +27,12 @@ constexpr uint32_t Z3 = BLOCK3 / 64;   // slices per workgroup of the step kerne
 
 }  // namespace
 
-// Six waves per SIMD for FP32 compute (80 VGPRs, some spilled to scratch):
-// the pair loop is latency-bound, and on grids with more wavefronts than
-// slots the extra waves hide more of it (128^3: 24 % faster than the 114
-// VGPRs of the unbounded build) than the scratch reloads cost.
+// Eight waves per SIMD (the most a SIMD holds) for FP32 compute: 64 VGPRs,
+// 67 more spilled to scratch. The pair loop is latency-bound, and the extra
+// waves hide more of it than the scratch reloads cost (128^3 FP32: 2.24 ms
+// against 2.63 at six waves and 3.21 at four).
 template <typename S>
-__global__ void __launch_bounds__(BLOCK3, (sizeof(S) == 8 ? 1 : 6))
+__global__ void __launch_bounds__(BLOCK3, (sizeof(S) == 8 ? 1 : 8))
 k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
        const GH3Consts<typename StepT<S>::type>* __restrict__ gc,
        const LatConsts<typename StepT<S>::type>* __restrict__ lc,
