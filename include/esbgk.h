@@ -285,9 +285,10 @@ const char* esbgk_batch_last_error(const esbgk_batch* b);
  * two), n_ref = N_L (0: nx, or the wall distance in nodes minus one with
  * walls). The
  * time step is dt = cfl dx / max|c| with dx = 1/N_L and 0 < cfl <= 1; the
- * largest root, and so dt, depends on the set. The axes' fluxes are summed
- * unsplit: a field that varies along d axes needs cfl <= 1/d (every abscissa
- * of these sets is nonzero), which is the caller's choice. */
+ * largest root, and so dt, depends on the set. Forward Euler on the
+ * collision and the unsplit sum of the axes' fluxes stays bounded while
+ * d cfl <= 1 - dt/tau for a field that varies along d axes (every abscissa
+ * of these sets is nonzero); that choice is the caller's. */
 typedef struct esbgk_tvd esbgk_tvd;
 
 /* Number of velocities Q, Hermite order N, abscissae c[Q][D] and weights

@@ -164,3 +164,41 @@ def test_shear_wave_decays_at_the_viscous_rate(gh):
     nu = 0.02                                  # Kn T^varpi / rho at rest
     err = [abs(r / (nu * k2) - 1.0) for r in rates]
     assert err[1] < 0.1 and err[1] < err[0]
+
+
+def test_unsplit_euler_stability_bound():
+    """The scheme of Sec. 3.1 applies forward Euler to the collision and the
+    advection together. With w = dt/tau, one step is a convex combination of
+    the equilibrium (weight w) and a TVD advection step whose Courant number
+    is sum|nu| / (1 - w), the sum taken over the axes along which the field
+    varies. So it stays bounded while sum|nu| <= 1 - w. Collision-free
+    advection is bounded up to sum|nu| = 1; with collisions the bound moves
+    in by w, and beyond it the noise grows without bound."""
+    gh4 = O.ProductSet(4, 2, 3)
+    Kn, Pr = 0.05, 2 / 3
+
+    def run(dims, cfl, kn, steps=400):
+        prob = O.TVDProblem(gh4, dims, Kn=kn, Pr=Pr, cfl=cfl, n_ref=max(dims), g=(0.0, 0.0, 0.0))
+        rng = np.random.default_rng(3)
+        M = prob.M
+        f = O.equilibrium_state(prob, np.ones(M), np.zeros((M, 2)), np.ones(M),
+                                rng.standard_normal((gh4.Q, M)), 0.02)
+        with np.errstate(all="ignore"):
+            g = O.run(f, prob, steps)
+        w = prob.dt * Pr / kn               # dt / tau at rho = T = 1
+        grew = not np.isfinite(g).all() or np.abs(g).max() > 10 * np.abs(f).max()
+        return w, grew, np.abs(f).max(), np.abs(g).max()
+
+    # collision-free: no new extrema up to a unit Courant number
+    w, grew, m0, m1 = run((1, 48), 1.0, 1e3)
+    assert w < 1e-4 and m1 <= m0
+    # 1-D field with collisions (w ~ 0.1)
+    w, grew, m0, m1 = run((1, 48), 0.85, Kn)
+    assert 0.85 <= 1 - w and m1 <= m0
+    w, grew, _, _ = run((1, 48), 0.95, Kn)
+    assert 0.95 > 1 - w and grew
+    # 2-D field: the two axes' Courant numbers add up
+    w, grew, m0, m1 = run((24, 24), 0.44, Kn)
+    assert 2 * 0.44 <= 1 - w and m1 <= m0
+    w, grew, _, _ = run((24, 24), 0.5, Kn)
+    assert 2 * 0.5 > 1 - w and grew
