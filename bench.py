@@ -308,7 +308,8 @@ def main():
     if args.profile:
         args.only_main, args.no_cpu = True, True
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library steps a lattice on one GPU (no halo exchange between GPUs "
+                                    "is implemented); --gpus must be 1"}))
         sys.exit(2)
 
     import torch
