@@ -89,9 +89,11 @@ k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
   GH3Collision<C> k;
   collision_gh3<C>(acc, lc, pp, k);
 
-  // pass 2: collision and fluxes, pair by pair
+  // pass 2: collision and fluxes, pair by pair, in the reverse of pass 1's
+  // order, so that it starts on the populations pass 1 read last (the pairs
+  // are independent: the order changes no result)
 #pragma unroll 1
-  for (int p = 0; p < P; ++p) {
+  for (int p = P - 1; p >= 0; --p) {
     const uint32_t pop = uint32_t(p) * pb;
     C hc[2];
     hc[0] = widen<C, S>(buf_ld<S>(row[2], xo[2], pop));
