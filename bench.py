@@ -114,7 +114,7 @@ def bench_tvd(storage, steps, warmup, velset="D2Q36GH", dims=None):
     name = TVD_CFG["name"].replace("d2q36", velset.lower())
     if dims != tuple(TVD_CFG["dims"]):
         name = f"periodic_gas_{'x'.join(map(str, dims))}_{velset.lower()}"
-    out = dict(workload=name, storage=storage, ms_per_step=ms,
+    out = dict(workload=name, storage=storage, cfl=round(cfl, 4), ms_per_step=ms,
                mlups=cells / (ms * 1e-3) / 1e6, algorithmic_GBs=2 * Q * s * cells / (ms * 1e-3) / 1e9,
                bytes_per_cell=2 * Q * s, kernel=f"k_tvd<{velset}, {storage}>", traffic=traffic,
                traffic_over_algorithmic=round(traffic / (2 * Q * s * cells), 4) if traffic else None,
