@@ -99,6 +99,17 @@ def test_channel_512x512x256_f16_one_step():
     _one_step_parity(cfg, "f16", steps_before=2)
 
 
+def test_slices_past_the_32bit_window_fp32():
+    """2048 x 2048 slices: seven slice blocks span more than 4 GiB, past the
+    32-bit offsets of the scalar-offset pull, so every wavefront pulls slice by
+    slice. One step at sampled cells (walls, edges, interior) against the oracle."""
+    from paper_1209_6548_amd import lattice_info, workloads
+    cfg = workloads.channel_3d(lattice_info("D3Q39")["r"], nx=2048, ny=2048, nz=8, storage="f32")
+    slice_block = (39 * 2048 * 2048 + 256) * 4
+    assert 7 * slice_block >= 1 << 32
+    _one_step_parity(cfg, "f32", steps_before=2)
+
+
 def test_couette_1x32_fp64_full_run():
     """The 1 x 32 Couette case for its full 20 000 steps, FP64, vs. the oracle."""
     from paper_1209_6548_amd import lattice_info, workloads
