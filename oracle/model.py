@@ -143,13 +143,3 @@ def raw_moments(f, c, order):
         out.append(np.einsum("qm,qi,qj,qk->mijk", f, c, c, c))
     return out
 
-
-def hermite_coefficients(f, c, N):
-    """eq. an on the quadrature: a^(n) = sum_alpha f_alpha chi^(n)(c_alpha),
-    n = 0..N; f (Q, M)."""
-    out = []
-    for n in range(N + 1):
-        x = hermite.chi(c, n)
-        Q = x.shape[0]
-        out.append((f.T @ x.reshape(Q, -1)).reshape((f.shape[1],) + x.shape[1:]))
-    return out
