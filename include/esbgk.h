@@ -177,7 +177,10 @@ int esbgk_step(esbgk_ctx* ctx, int64_t n);
 /* Runs of `steps` consecutive step launches (even, default 32) are captured
  * once per starting buffer in a HIP graph and replayed on the handle's
  * stream; 0 disables graphs (one launch per step). Steps that carry a fused
- * reduction are always launched directly. Results are identical either way. */
+ * reduction are always launched directly. Results are identical either way.
+ * Changing the length (and esbgk_set_wall_heating switching heating on or
+ * off, and esbgk_destroy) first waits for the handle's stream, so that no
+ * replay is queued or running when its graph is released. */
 int esbgk_set_graph_steps(esbgk_ctx* ctx, int steps);
 
 /* Macroscopic fields of eq. mac at the current level, FP64 [F][cells] host:
@@ -221,7 +224,12 @@ typedef struct {
                                  esbgk_set_wall_accommodation) */
 } esbgk_problem;
 
+/* Bytes of device workspace for the batch (0 if a problem is invalid). */
 size_t esbgk_batch_workspace_bytes(const esbgk_problem* problems, int n);
+/* New batch handle on a caller-allocated, 256-byte-aligned workspace and a
+ * HIP stream. Errors: E_INVALID (a problem's shape, gas or walls),
+ * E_UNSTABLE (an ESBGK_EULER problem with dt/tau or dt/(Pr tau) >= 2 at
+ * rho = T = 1, as esbgk_set_gas), E_NOMEM (workspace), E_HIP. */
 int esbgk_batch_create(const esbgk_problem* problems, int n, void* d_workspace,
                        size_t ws_bytes, void* hip_stream, esbgk_batch** out);
 int esbgk_batch_destroy(esbgk_batch* b);
@@ -229,8 +237,35 @@ int esbgk_batch_destroy(esbgk_batch* b);
  * noise holds Q * (sum of all cells) values, problem after problem, each
  * [Q][cells]). */
 int esbgk_batch_init_equilibrium(esbgk_batch* b, const double* noise, double amplitude);
-/* Advance every problem n steps in one persistent launch (asynchronous). */
+/* Advance every problem n steps in one persistent launch (asynchronous). The
+ * launch (the persistent kernel, then the update of the device step counter
+ * it reads its starting level from) is captured in a HIP graph the first
+ * time a step count n is used and replayed afterwards; the graphs are
+ * released (after waiting for the stream) when the layout or the reduction
+ * interval changes. */
 int esbgk_batch_step(esbgk_batch* b, int64_t n);
+/* on = 0: launch directly instead of replaying captured graphs (the same
+ * kernels and results); on = 1 (default): replay. */
+int esbgk_batch_use_graphs(esbgk_batch* b, int on);
+/* FP64 reductions of every problem, as esbgk_reduce does for one lattice:
+ * out[8 * i + k] for problem i holds its mass sum rho, energy
+ * sum 1/2 sum_alpha f c^2, momentum sum rho u (3), mass flow rate through a
+ * plane normal to x, dx^(D-1)/nx sum rho u_x, the residual
+ * ||u - u_prev||_2/||u||_2 since the problem's previous reduction (0 for the
+ * first after the state was set) and the level the sums belong to.
+ * esbgk_batch_set_reduce_interval(R > 0) fuses them into the persistent
+ * kernel's steps from levels R-1, 2R-1, ... (0 disables): the step's
+ * reconstructed state, per-cell terms in FP64, summed per 64-cell chunk by a
+ * wavefront butterfly and then over the problem's chunks in order by one
+ * thread of the workgroup that owns the problem (deterministic; no
+ * atomics). esbgk_batch_reduce forms them now from the stored state in FP64
+ * arithmetic and synchronises; esbgk_batch_last_reduction returns the latest
+ * of either kind and synchronises (E_STATE if none has run since the state
+ * was set). E_NONFINITE (sticky) if a cell of some problem has a non-finite
+ * value, rho <= 0 or T <= 0. out holds 8 * (number of problems) doubles. */
+int esbgk_batch_set_reduce_interval(esbgk_batch* b, int64_t R);
+int esbgk_batch_reduce(esbgk_batch* b, double* out);
+int esbgk_batch_last_reduction(esbgk_batch* b, double* out);
 /* Fields of problem i (same layout as esbgk_read_moments); synchronises. */
 int esbgk_batch_read_moments(esbgk_batch* b, int i, double* h_out, int* F);
 /* Stored populations of problem i as FP64 h[Q][cells_i]; synchronises. */
@@ -241,10 +276,15 @@ int esbgk_batch_get_populations(esbgk_batch* b, int i, double* h);
  * the largest workgroup and one bin per resident workgroup. */
 int esbgk_batch_set_layout(esbgk_batch* b, int threads, int nbins);
 int esbgk_batch_layout(const esbgk_batch* b, int* threads, int* nbins);
+/* Shape of the current layout: the most problems one workgroup owns, and the
+ * most cells one thread updates per step (a bin's thread slots, each problem
+ * rounded up to 64 cells, over the workgroup size). Either output may be
+ * NULL. */
+int esbgk_batch_layout_info(const esbgk_batch* b, int* max_problems_per_bin, int64_t* max_cells_per_thread);
 /* Autotuner: time steps_per_trial steps of every candidate layout
- * (workgroups of 256..max threads x 1, 2, 4, 8 bins per compute unit) on the
- * uniform rest state and keep the fastest. Overwrites the state: call
- * esbgk_batch_init_equilibrium afterwards. */
+ * (workgroups of 256..max threads x 1, 2, 4, 8 bins per compute unit or one
+ * problem per workgroup) on the uniform rest state and keep the fastest.
+ * Overwrites the state: call esbgk_batch_init_equilibrium afterwards. */
 int esbgk_batch_autotune(esbgk_batch* b, int steps_per_trial);
 int64_t esbgk_batch_steps_done(const esbgk_batch* b);
 const char* esbgk_batch_last_error(const esbgk_batch* b);
@@ -310,6 +350,17 @@ int esbgk_tvd_create(const esbgk_shape* shape, double cfl, void* d_workspace, si
 int esbgk_tvd_destroy(esbgk_tvd* t);
 /* dt of the handle (nondimensional). */
 double esbgk_tvd_time_step(const esbgk_tvd* t);
+/* Boundedness of the TVD step (Sec. 3.1 update with forward Euler on the
+ * collision): with w = dt/tau at rho = T = 1 (dt = cfl / (n_ref max|c|),
+ * tau = Kn/Pr), one step is a convex combination of the equilibrium (weight
+ * w) and a TVD advection step whose Courant number is the sum of |nu| over
+ * the axes the field varies along, so it stays bounded while
+ * axes * cfl <= 1 - w (every abscissa of these sets is nonzero). Returns
+ * ESBGK_OK when that holds, ESBGK_E_UNSTABLE when it does not, ESBGK_E_INVALID
+ * for an unknown set, n_ref < 1, cfl outside (0, 1], Kn <= 0, Pr < 2/3 or
+ * axes outside [1, D]. Touches no GPU; the library does not enforce it (the
+ * number of axes the field varies along is the caller's knowledge). */
+int esbgk_tvd_bounded(int velset, int n_ref, double cfl, double Kn, double Pr, int axes);
 /* Gas (as esbgk_set_gas); E_UNSTABLE when forward Euler is unstable at
  * rho = T = 1 (dt/tau >= 2 or dt/(Pr tau) >= 2). */
 int esbgk_tvd_set_gas(esbgk_tvd* t, double Kn, double Pr, double varpi);

@@ -97,6 +97,11 @@ def lib():
             "esbgk_batch_layout": (I, [P, P, P]),
             "esbgk_batch_autotune": (I, [P, I]),
             "esbgk_batch_steps_done": (I64, [P]),
+            "esbgk_batch_use_graphs": (I, [P, I]),
+            "esbgk_batch_set_reduce_interval": (I, [P, I64]),
+            "esbgk_batch_reduce": (I, [P, DP]),
+            "esbgk_batch_last_reduction": (I, [P, DP]),
+            "esbgk_batch_layout_info": (I, [P, P, P]),
             "esbgk_batch_last_error": (ctypes.c_char_p, [P]),
             "esbgk_tvd_info": (I, [DP, DP]),
             "esbgk_tvd_set_info": (I, [I, P, P, DP, DP]),
@@ -104,6 +109,7 @@ def lib():
             "esbgk_tvd_create": (I, [P, D, P, SZ, P, P]),
             "esbgk_tvd_destroy": (I, [P]),
             "esbgk_tvd_time_step": (D, [P]),
+            "esbgk_tvd_bounded": (I, [I, I, D, D, D, I]),
             "esbgk_tvd_set_gas": (I, [P, D, D, D]),
             "esbgk_tvd_set_body_force": (I, [P, DP]),
             "esbgk_tvd_set_wall": (I, [P, I, D, DP]),
@@ -379,6 +385,38 @@ class Batch:
     def step(self, n=1):
         self._check(lib().esbgk_batch_step(self._b, int(n)), "batch_step")
 
+    @property
+    def steps_done(self):
+        return lib().esbgk_batch_steps_done(self._b)
+
+    def use_graphs(self, on):
+        self._check(lib().esbgk_batch_use_graphs(self._b, int(bool(on))), "batch_use_graphs")
+
+    def layout_info(self):
+        mp, mc = ctypes.c_int(), ctypes.c_int64()
+        self._check(lib().esbgk_batch_layout_info(self._b, ctypes.byref(mp), ctypes.byref(mc)), "batch_layout_info")
+        t, nb = self.layout()
+        return dict(threads=t, bins=nb, max_problems_per_workgroup=mp.value, max_cells_per_thread=mc.value)
+
+    def set_reduce_interval(self, R):
+        self._check(lib().esbgk_batch_set_reduce_interval(self._b, int(R)), "batch_set_reduce_interval")
+
+    @staticmethod
+    def _reds(out):
+        return [dict(mass=o[0], energy=o[1], mom=o[2:5].copy(), mdot=o[5], residual=o[6], step=int(o[7]))
+                for o in out.reshape(-1, 8)]
+
+    def reduce(self):
+        """FP64 reductions of every problem at the current level (list of dicts)."""
+        out = np.empty(8 * self.n)
+        self._check(lib().esbgk_batch_reduce(self._b, _dp(out)), "batch_reduce")
+        return self._reds(out)
+
+    def last_reduction(self):
+        out = np.empty(8 * self.n)
+        self._check(lib().esbgk_batch_last_reduction(self._b, _dp(out)), "batch_last_reduction")
+        return self._reds(out)
+
     def read_moments(self, i):
         F = 9 if self.D == 2 else 14
         out = np.empty((F, self.cells[i]))
@@ -409,6 +447,19 @@ def tvd_velocity_set(velset="D2Q36GH"):
     return c, w
 
 
+def default_tvd_cfl(D):
+    """Default Courant number of the TVD scheme: 0.45 in 2-D, 0.3 in 3-D, so
+    that the Courant numbers of a field varying along every axis sum to 0.9."""
+    return 0.45 if D == 2 else 0.3
+
+
+def tvd_bounded(velset, n_ref, cfl, Kn, Pr, axes):
+    """esbgk_tvd_bounded: OK (0) when axes * cfl <= 1 - dt/tau at rho = T = 1
+    (forward Euler on the collision and the unsplit flux sum stays a convex
+    combination), E_UNSTABLE otherwise, E_INVALID for bad arguments."""
+    return lib().esbgk_tvd_bounded(_GH_SET[velset], int(n_ref), float(cfl), float(Kn), float(Pr), int(axes))
+
+
 class TVDLattice:
     """The paper's own scheme (forward Euler, TVD minmod fluxes) on a
     Gauss-Hermite product set (the paper's D2Q36GH by default; D2Q16GH and
@@ -416,11 +467,17 @@ class TVDLattice:
     nz): periodic in every axis but the last, which is periodic or
     (walls=True) bounded by diffuse walls on its first and last nodes."""
 
-    def __init__(self, nx=64, ny=64, storage="f32", cfl=0.5, n_ref=0, walls=False, velset="D2Q36GH",
+    def __init__(self, nx=64, ny=64, storage="f32", cfl=None, n_ref=0, walls=False, velset="D2Q36GH",
                  device="cuda:0", nz=1):
         import torch
         self.device = torch.device(device)
         self.D = 3 if velset == "D3Q216GH" else 2
+        # default Courant number inside the bound of tvd_bounded for a field
+        # that varies along every axis (sum of |nu| = 0.9)
+        cfl = default_tvd_cfl(self.D) if cfl is None else cfl
+        self.cfl = float(cfl)
+        nwall = ny if self.D == 2 else nz
+        self.n_ref = n_ref if n_ref > 0 else (nwall - 1 if walls else nx)
         self.dims = (nx, ny) if self.D == 2 else (nx, ny, nz)
         self.cells = nx * ny * nz
         self.storage = storage
@@ -470,6 +527,11 @@ class TVDLattice:
 
     def set_gas(self, Kn, Pr, varpi=0.5):
         self._check(lib().esbgk_tvd_set_gas(self._t, Kn, Pr, varpi), "tvd_set_gas")
+        axes = sum(1 for n in self.dims if n > 1)
+        if axes and tvd_bounded(self.velset, self.n_ref, self.cfl, Kn, Pr, axes) == E_UNSTABLE:
+            import warnings
+            warnings.warn(f"TVD step not bounded for a field varying along {axes} axes: {axes} * cfl = "
+                          f"{axes * self.cfl:.3g} > 1 - dt/tau", RuntimeWarning, stacklevel=2)
 
     def set_body_force(self, g):
         gg = np.zeros(3)

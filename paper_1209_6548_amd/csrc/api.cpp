@@ -182,6 +182,10 @@ StepArgs args_at(const esbgk_ctx* c, int cur) {
   a.uprev = c->at(c->lay.uprev);
   a.have_prev = c->have_prev;
   a.reduce = 0;
+  // alternate the tile order between the two buffers for FP32 storage
+  // (measured on MI355X at 1024 x 1024: 2-3 % faster for FP32, 5 % slower
+  // for FP16 whose lattice fits the memory-side cache, no change for FP64)
+  a.rev = c->shape.storage == ESBGK_F32 ? cur : 0;
   a.red_part = reinterpret_cast<double*>(c->at(c->lay.red_part));
   a.stream = c->stream;
   return a;
@@ -206,7 +210,13 @@ int sync_level(esbgk_ctx* c) {
 }
 
 
+// A replay may still be queued or running on the caller's stream (esbgk_step
+// returns after hipGraphLaunch): wait for it before the executable graphs go.
 void drop_graphs(esbgk_ctx* c) {
+  if ((c->graph[0] || c->graph[1]) && hipStreamSynchronize(c->stream) != hipSuccess) {
+    c->sticky = ESBGK_E_HIP;
+    c->err = "synchronize before releasing the step graphs failed";
+  }
   for (int p = 0; p < 2; ++p) {
     if (c->graph[p]) (void)hipGraphExecDestroy(c->graph[p]);
     c->graph[p] = nullptr;

@@ -18,9 +18,29 @@ constexpr int BATCH_MAX_PER_BIN = 64;
 
 struct BatchProblem {
   Geometry geo;
-  uint64_t pop_off;   // element offset of the problem's [Q][cells] block
-  uint32_t wp_off;    // element offset of its wall partial sums [2][3][ncols]
-  uint32_t pad;
+  uint64_t pop_off;    // element offset of the problem's [Q][cells] block
+  uint64_t cell_off;   // first cell of the problem in the batch's cell numbering (u_prev: [D][cells] from D*cell_off)
+  uint32_t wp_off;     // element offset of its wall partial sums [2][3][ncols]
+  uint32_t chunk_off;  // first 64-cell chunk of the problem (reduction partials)
+};
+
+// FP64 reductions of the batch (per problem, NRED sums each):
+//   level      device step counter: the level the next launch starts from
+//   R          fuse the reductions into the steps from levels R-1, 2R-1, ...
+//              (0: never)
+//   uprev      [D][cells] per problem (compute type): u of the problem's
+//              previous reduction, for the residual
+//   chunks     [chunks][NRED]: wavefront partials of 64-cell chunks
+//   out        [problems][NRED]: sums of the latest reduction
+//   red_level  [problems]: level of the latest reduction (-1: none since the
+//              state was set)
+struct BatchRed {
+  const int64_t* level;
+  int64_t R;
+  void* uprev;
+  double* chunks;
+  double* out;
+  int64_t* red_level;
 };
 
 struct BatchLaunch {
@@ -28,17 +48,24 @@ struct BatchLaunch {
   const void* pps;            // ProbParams<C>[n]
   const uint32_t* bin_first;  // [nbins + 1] into order
   const uint32_t* order;      // problem ids grouped by bin
-  void* bufA;
+  void* bufA;                 // the state of an even level is in A, of an odd level in B
   void* bufB;
   void* wpA;
   void* wpB;
   const void* lc;
   int64_t nsteps;
-  int parity;                 // 0: the current state is in A; 1: in B
+  BatchRed red;
   uint32_t nbins, threads;
   hipStream_t stream;
 };
 
+// The persistent step kernel (nsteps steps from level *red.level), then the
+// level advanced by nsteps.
 hipError_t launch_batch(int velset, int storage, const BatchLaunch& a);
+// FP64 reductions of every problem at the current level (*red.level) from the
+// stored state (no step), recorded as at level `level`; pps/lc are the FP64
+// parameter blocks.
+hipError_t launch_batch_reduce(int velset, int storage, const BatchLaunch& a, const void* pps64,
+                               const void* lc64, int64_t level);
 
 }  // namespace esbgk

@@ -10,10 +10,19 @@
 // the bin advances n steps in one launch with no host round trip. The
 // barrier's workgroup-scope release/acquire makes the global-memory writes of
 // one step visible to every wave of the workgroup in the next.
+//
+// FP64 reductions. A step from a level that is one less than a multiple of R
+// also sums, per problem, the FP64 contributions of its cells' reconstructed
+// state (mass, energy, momentum, residual terms): each wavefront reduces its
+// 64-cell chunk with a butterfly and writes the chunk's partial; after the
+// step's barrier one thread per problem adds the problem's chunk partials in
+// chunk order. Every problem belongs to one workgroup, so the sums need no
+// atomics and do not depend on the scheduling: they are deterministic.
 
 #include <hip/hip_runtime.h>
 
 #include "batch.h"
+#include "reduce.h"
 #include "stream.h"
 
 namespace esbgk {
@@ -22,7 +31,7 @@ template <class L, typename S, typename C>
 __device__ __forceinline__ void batch_cell(const BatchProblem& bp, uint32_t cell, const S* __restrict__ srcb,
                                            S* __restrict__ dstb, const C* __restrict__ wpsb, C* __restrict__ wpdb,
                                            const LatConsts<C>* __restrict__ lc,
-                                           const ProbParams<C>* __restrict__ pp) {
+                                           const ProbParams<C>* __restrict__ pp, CellState<L, C>& st) {
   const Geometry& geo = bp.geo;
   const S* src = srcb + bp.pop_off;
   S* dst = dstb + bp.pop_off;
@@ -31,7 +40,6 @@ __device__ __forceinline__ void batch_cell(const BatchProblem& bp, uint32_t cell
   const CellPos p = cell_pos(cell, geo);
   C h[L::Q];
   gather_lane<L, S, C, C, uint32_t>(h, src, geo, p, wps, pp);
-  CellState<L, C> st;
   collide<L, C>(h, lc, pp, st);
   const uint32_t elem = uint32_t(cell_elem<L>(p, geo));
 #pragma unroll
@@ -39,51 +47,167 @@ __device__ __forceinline__ void batch_cell(const BatchProblem& bp, uint32_t cell
   write_wall_partials<L, S, C>([&](int a) { return narrow<S, C>(h[a]); }, p, geo, lc, wpd);
 }
 
+// Bin bookkeeping shared by the step and reduction kernels: the problems of
+// the workgroup's bin and their first thread slots (multiples of 64).
+struct BinTable {
+  uint32_t cum[BATCH_MAX_PER_BIN + 1];
+  uint32_t pid[BATCH_MAX_PER_BIN];
+};
+
+__device__ __forceinline__ uint32_t load_bin(BinTable& bt, const BatchProblem* __restrict__ probs,
+                                             const uint32_t* __restrict__ bin_first,
+                                             const uint32_t* __restrict__ order) {
+  const uint32_t p0 = bin_first[blockIdx.x], p1 = bin_first[blockIdx.x + 1];
+  const uint32_t np = p1 - p0;
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (uint32_t k = 0; k < np; ++k) {
+      const uint32_t id = order[p0 + k];
+      bt.pid[k] = id;
+      bt.cum[k] = acc;
+      acc += (probs[id].geo.ncells + 63u) & ~63u;
+    }
+    bt.cum[np] = acc;
+  }
+  __syncthreads();
+  return np;
+}
+
+// Index k of the bin's problem whose slots hold t0 (cum[k] <= t0 < cum[k+1]);
+// t0 is wavefront-uniform, so the search runs on scalars.
+__device__ __forceinline__ uint32_t find_problem(const BinTable& bt, uint32_t np, uint32_t t0) {
+  uint32_t k = 0, hi = np;
+  while (hi - k > 1) {
+    const uint32_t mid = (k + hi) >> 1;
+    if (__builtin_amdgcn_readfirstlane(bt.cum[mid]) <= t0) k = mid;
+    else hi = mid;
+  }
+  return k;
+}
+
+// Butterfly over the wavefront; lane 0 writes the chunk's NRED partials.
+__device__ __forceinline__ void write_chunk(double (&v)[NRED], double* __restrict__ dst) {
+#pragma unroll
+  for (int k = 0; k < NRED; ++k) v[k] = wave_sum(v[k]);
+  if ((threadIdx.x & 63u) == 0) {
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) dst[k] = v[k];
+  }
+}
+
+// After the barrier that follows the chunk writes: thread k < np adds the
+// chunk partials of the bin's k-th problem in chunk order.
+__device__ __forceinline__ void sum_problems(const BinTable& bt, uint32_t np, const BatchProblem* __restrict__ probs,
+                                             const BatchRed& red, int64_t level) {
+  if (threadIdx.x < np) {
+    const uint32_t id = bt.pid[threadIdx.x];
+    const BatchProblem& bp = probs[id];
+    const uint32_t nch = (bp.geo.ncells + 63u) >> 6;
+    double acc[NRED];
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
+    for (uint32_t c = 0; c < nch; ++c) {
+      const double* q = red.chunks + size_t(bp.chunk_off + c) * NRED;
+#pragma unroll
+      for (int k = 0; k < NRED; ++k) acc[k] += q[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) red.out[size_t(id) * NRED + k] = acc[k];
+    red.red_level[id] = level;
+  }
+}
+
 template <class L, typename S, typename C, int MAXT>
 __global__ void __launch_bounds__(MAXT)
 k_batch(const BatchProblem* __restrict__ probs, const ProbParams<C>* __restrict__ pps,
         const uint32_t* __restrict__ bin_first, const uint32_t* __restrict__ order, S* __restrict__ bufA,
         S* __restrict__ bufB, C* __restrict__ wpA, C* __restrict__ wpB, const LatConsts<C>* __restrict__ lc,
-        int64_t nsteps, int parity) {
-  __shared__ uint32_t cum[BATCH_MAX_PER_BIN + 1];
-  __shared__ uint32_t pid[BATCH_MAX_PER_BIN];
-  const uint32_t p0 = bin_first[blockIdx.x], p1 = bin_first[blockIdx.x + 1];
-  const uint32_t np = p1 - p0;
-  // slots of the bin: each problem's cells start on a multiple of 64, so that
-  // every wavefront's 64 slots lie in one problem, whose descriptor and
-  // parameter block the wavefront then reads as scalars
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (uint32_t k = 0; k < np; ++k) {
-      const uint32_t id = order[p0 + k];
-      pid[k] = id;
-      cum[k] = acc;
-      acc += (probs[id].geo.ncells + 63u) & ~63u;
-    }
-    cum[np] = acc;
-  }
-  __syncthreads();
-  const uint32_t total = cum[np];
+        int64_t nsteps, BatchRed red) {
+  __shared__ BinTable bt;
+  const uint32_t np = load_bin(bt, probs, bin_first, order);
+  const uint32_t total = bt.cum[np];
   const uint32_t lane = threadIdx.x & 63u;
+  const int64_t level0 = *red.level;
+  C* uprev = static_cast<C*>(red.uprev);
   for (int64_t s = 0; s < nsteps; ++s) {
-    const bool odd = ((s + parity) & 1) != 0;
+    const int64_t lev = level0 + s;
+    const bool odd = (lev & 1) != 0;
+    const bool rstep = red.R > 0 && (lev + 1) % red.R == 0;
     const S* src = odd ? bufB : bufA;
     S* dst = odd ? bufA : bufB;
     const C* wps = odd ? wpB : wpA;
     C* wpd = odd ? wpA : wpB;
     for (uint32_t t0 = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u); t0 < total; t0 += blockDim.x) {
-      uint32_t k = 0, hi = np;   // cum[k] <= t0 < cum[k + 1]
-      while (hi - k > 1) {
-        const uint32_t mid = (k + hi) >> 1;
-        if (__builtin_amdgcn_readfirstlane(cum[mid]) <= t0) k = mid;
-        else hi = mid;
+      const uint32_t k = find_problem(bt, np, t0);
+      const uint32_t id = __builtin_amdgcn_readfirstlane(bt.pid[k]);
+      const uint32_t first = __builtin_amdgcn_readfirstlane(bt.cum[k]);
+      const uint32_t cell = t0 - first + lane;
+      const BatchProblem& bp = probs[id];
+      double v[NRED];
+#pragma unroll
+      for (int q = 0; q < NRED; ++q) v[q] = 0.0;
+      if (cell < bp.geo.ncells) {
+        CellState<L, C> st;
+        batch_cell<L, S, C>(bp, cell, src, dst, wps, wpd, lc, pps + id, st);
+        if (rstep)
+          cell_contrib<L, C, C>(st, uprev + size_t(L::D) * bp.cell_off, cell, bp.geo.ncells,
+                                red.red_level[id] >= 0, v);
       }
-      const uint32_t id = __builtin_amdgcn_readfirstlane(pid[k]);
-      const uint32_t cell = t0 - __builtin_amdgcn_readfirstlane(cum[k]) + lane;
-      if (cell < probs[id].geo.ncells) batch_cell<L, S, C>(probs[id], cell, src, dst, wps, wpd, lc, pps + id);
+      if (rstep) write_chunk(v, red.chunks + size_t(bp.chunk_off + ((t0 - first) >> 6)) * NRED);
     }
     __syncthreads();
+    if (rstep) {
+      sum_problems(bt, np, probs, red, lev);
+      __syncthreads();
+    }
   }
+}
+
+// FP64 reductions of the stored state of level `level` (no step): FP64
+// pull and reconstruction, as the single-lattice read-out kernels.
+template <class L, typename S, typename P, int MAXT>
+__global__ void __launch_bounds__(MAXT)
+k_batch_reduce(const BatchProblem* __restrict__ probs, const ProbParams<double>* __restrict__ pps,
+               const uint32_t* __restrict__ bin_first, const uint32_t* __restrict__ order,
+               const S* __restrict__ bufA, const S* __restrict__ bufB, const P* __restrict__ wpA,
+               const P* __restrict__ wpB, const LatConsts<double>* __restrict__ lc, BatchRed red, int64_t level) {
+  __shared__ BinTable bt;
+  const uint32_t np = load_bin(bt, probs, bin_first, order);
+  const uint32_t total = bt.cum[np];
+  const uint32_t lane = threadIdx.x & 63u;
+  const bool odd = (level & 1) != 0;
+  const S* srcb = odd ? bufB : bufA;
+  const P* wpsb = odd ? wpB : wpA;
+  P* uprev = static_cast<P*>(red.uprev);
+  for (uint32_t t0 = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u); t0 < total; t0 += blockDim.x) {
+    const uint32_t k = find_problem(bt, np, t0);
+    const uint32_t id = __builtin_amdgcn_readfirstlane(bt.pid[k]);
+    const uint32_t first = __builtin_amdgcn_readfirstlane(bt.cum[k]);
+    const uint32_t cell = t0 - first + lane;
+    const BatchProblem& bp = probs[id];
+    double v[NRED];
+#pragma unroll
+    for (int q = 0; q < NRED; ++q) v[q] = 0.0;
+    if (cell < bp.geo.ncells) {
+      const CellPos p = cell_pos(cell, bp.geo);
+      double h[L::Q];
+      gather_lane<L, S, double, P, uint32_t>(h, srcb + bp.pop_off, bp.geo, p, wpsb + bp.wp_off, pps + id);
+      RawMoments<L, double> m;
+      raw_moments<L, double>(h, lc, false, m);
+      CellState<L, double> st;
+      reconstruct<L, double>(m, lc, pps + id, st);
+      cell_contrib<L, double, P>(st, uprev + size_t(L::D) * bp.cell_off, cell, bp.geo.ncells,
+                                 red.red_level[id] >= 0, v);
+    }
+    write_chunk(v, red.chunks + size_t(bp.chunk_off + ((t0 - first) >> 6)) * NRED);
+  }
+  __syncthreads();
+  sum_problems(bt, np, probs, red, level);
+}
+
+// Move the device level on by n after a launch (one thread).
+__global__ void k_batch_advance(int64_t* __restrict__ level, int64_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *level += n;
 }
 
 template <class L, typename S, typename C>
@@ -93,7 +217,25 @@ static hipError_t batch_t(const BatchLaunch& a) {
   hipLaunchKernelGGL((k_batch<L, S, C, MAXT>), dim3(a.nbins), dim3(a.threads), 0, a.stream, a.probs,
                      static_cast<const ProbParams<C>*>(a.pps), a.bin_first, a.order, static_cast<S*>(a.bufA),
                      static_cast<S*>(a.bufB), static_cast<C*>(a.wpA), static_cast<C*>(a.wpB),
-                     static_cast<const LatConsts<C>*>(a.lc), a.nsteps, a.parity);
+                     static_cast<const LatConsts<C>*>(a.lc), a.nsteps, a.red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, a.stream, const_cast<int64_t*>(a.red.level), a.nsteps);
+  return hipGetLastError();
+}
+
+// The reduction kernel runs FP64 arithmetic: workgroups of 256 threads keep
+// it free of scratch (any workgroup size covers a bin).
+constexpr int BATCH_REDUCE_THREADS = 256;
+
+template <class L, typename S, typename C>
+static hipError_t batch_reduce_t(const BatchLaunch& a, const void* pps64, const void* lc64, int64_t level) {
+  constexpr int T = BATCH_REDUCE_THREADS;
+  static_assert(T >= BATCH_MAX_PER_BIN, "one thread per problem of a bin sums its chunks");
+  hipLaunchKernelGGL((k_batch_reduce<L, S, C, T>), dim3(a.nbins), dim3(T), 0, a.stream, a.probs,
+                     static_cast<const ProbParams<double>*>(pps64), a.bin_first, a.order,
+                     static_cast<const S*>(a.bufA), static_cast<const S*>(a.bufB), static_cast<const C*>(a.wpA),
+                     static_cast<const C*>(a.wpB), static_cast<const LatConsts<double>*>(lc64), a.red, level);
   return hipGetLastError();
 }
 
@@ -106,6 +248,20 @@ hipError_t launch_batch(int velset, int storage, const BatchLaunch& a) {
     if (storage == 0) return batch_t<D3Q39, double, double>(a);
     if (storage == 1) return batch_t<D3Q39, float, float>(a);
     if (storage == 2) return batch_t<D3Q39, _Float16, float>(a);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_reduce(int velset, int storage, const BatchLaunch& a, const void* pps64, const void* lc64,
+                               int64_t level) {
+  if (velset == 1) {
+    if (storage == 0) return batch_reduce_t<D2Q37, double, double>(a, pps64, lc64, level);
+    if (storage == 1) return batch_reduce_t<D2Q37, float, float>(a, pps64, lc64, level);
+    if (storage == 2) return batch_reduce_t<D2Q37, _Float16, float>(a, pps64, lc64, level);
+  } else if (velset == 2) {
+    if (storage == 0) return batch_reduce_t<D3Q39, double, double>(a, pps64, lc64, level);
+    if (storage == 1) return batch_reduce_t<D3Q39, float, float>(a, pps64, lc64, level);
+    if (storage == 2) return batch_reduce_t<D3Q39, _Float16, float>(a, pps64, lc64, level);
   }
   return hipErrorInvalidValue;
 }

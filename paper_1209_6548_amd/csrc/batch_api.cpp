@@ -30,8 +30,11 @@ size_t csize(int storage) { return storage == ESBGK_F64 ? 8 : 4; }
 
 struct BLayout {
   size_t bufA, bufB, wpA, wpB, probs, pps, lc, pps64, lc64, bin_first, order, staging, total;
+  size_t uprev, chunks, red_out, red_level, level;
   size_t pop_elems, wp_elems;
 };
+
+constexpr const char* UNSTABLE_MSG = "Euler step unstable: dt/tau or dt/(Pr tau) >= 2";
 
 bool valid_problem(const esbgk_problem& p, const esbgk_problem& first, std::string* why) {
   auto fail = [&](const char* m) { if (why) *why = m; return false; };
@@ -50,6 +53,14 @@ bool valid_problem(const esbgk_problem& p, const esbgk_problem& first, std::stri
   if (s.storage < 0 || s.storage > 2 || (s.scheme != 0 && s.scheme != 1) || s.n_ref < 0) return fail("bad shape");
   if (!(p.Kn > 0.0) || !(p.Pr >= 2.0 / 3.0 - 1e-12) || !(p.varpi >= 0.5 && p.varpi <= 1.0))
     return fail("bad gas parameters");
+  if (s.scheme == ESBGK_EULER) {
+    // forward Euler along the characteristic needs dt/tau < 2 and
+    // dt/(Pr tau) < 2 at rho = T = 1 (dt = dx/r, dx = 1/N_L)
+    const HostLattice* lat = host_lattice(s.velset);
+    const int nref = s.n_ref > 0 ? s.n_ref : nw;
+    const double dt = 1.0 / (double(nref) * (lat ? lat->r : 1.0));
+    if (!(dt * p.Pr / p.Kn < 2.0 && dt / p.Kn < 2.0)) return fail(UNSTABLE_MSG);
+  }
   const int W = s.velset == ESBGK_D2Q37 ? 1 : 2;   // wall-normal axis
   for (int side = 0; side < 2; ++side) {
     if (!(p.T_w[side] > 0.0)) return fail("T_w must be > 0");
@@ -66,12 +77,14 @@ BLayout blayout(const esbgk_problem* p, int n) {
   const HostLattice* lat = host_lattice(p[0].shape.velset);
   const int storage = p[0].shape.storage;
   BLayout L{};
-  size_t pop = 0, wp = 0, maxc = 0;
+  size_t pop = 0, wp = 0, maxc = 0, cells = 0, chunks = 0;
   for (int i = 0; i < n; ++i) {
     pop += size_t(lat->Q) * cells_of(p[i].shape);
     pop = (pop + 63) / 64 * 64;
     wp += 6 * size_t(ncols_of(p[i].shape));
     maxc = std::max<size_t>(maxc, cells_of(p[i].shape));
+    cells += cells_of(p[i].shape);
+    chunks += (cells_of(p[i].shape) + 63) / 64;
   }
   L.pop_elems = pop;
   L.wp_elems = wp;
@@ -89,6 +102,11 @@ BLayout blayout(const esbgk_problem* p, int n) {
   L.lc64 = csize(storage) == 8 ? L.lc : take(sizeof(LatConsts<double>));
   L.bin_first = take(size_t(n + 1) * 4);
   L.order = take(size_t(n) * 4);
+  L.uprev = take(size_t(lat->D) * cells * csize(storage));
+  L.chunks = take(chunks * NRED * sizeof(double));
+  L.red_out = take(size_t(n) * NRED * sizeof(double));
+  L.red_level = take(size_t(n) * sizeof(int64_t));
+  L.level = take(sizeof(int64_t));
   const size_t sc = std::min<size_t>(maxc, STAGE_CELLS);
   L.staging = take(sc * std::max<size_t>(nfields(lat->D), size_t(lat->Q)) * 8);
   L.total = off;
@@ -112,6 +130,14 @@ struct esbgk_batch {
   int cus = 0;
   int sticky = 0;
   std::string err;
+  int64_t R = 0;               // fused reduction interval (0: none)
+  // the persistent launch (kernel + level update) captured once per step
+  // count n and replayed; released when the launch changes (layout, R)
+  bool use_graphs = true;
+  hipStream_t cap = nullptr;
+  std::vector<std::pair<int64_t, hipGraphExec_t>> graphs;
+  std::vector<uint64_t> bin_slots;   // thread slots (cells rounded up to 64 per problem) of each bin
+  std::vector<uint32_t> bin_count;   // problems of each bin
   char* at(size_t o) const { return ws + o; }
 };
 
@@ -158,9 +184,15 @@ int build_bins(esbgk_batch* b, uint32_t nbins) {
   }
   std::vector<uint32_t> first(nbins + 1), order;
   order.reserve(n);
+  b->bin_slots.assign(nbins, 0);
+  b->bin_count.assign(nbins, 0);
   for (uint32_t k = 0; k < nbins; ++k) {
     first[k] = uint32_t(order.size());
-    for (uint32_t id : bins[k]) order.push_back(id);
+    for (uint32_t id : bins[k]) {
+      order.push_back(id);
+      b->bin_slots[k] += (b->bp[id].geo.ncells + 63u) & ~63u;
+    }
+    b->bin_count[k] = uint32_t(bins[k].size());
   }
   first[nbins] = uint32_t(order.size());
   BHIP(b, hipMemcpyAsync(b->at(b->lay.bin_first), first.data(), first.size() * 4, hipMemcpyHostToDevice, b->stream),
@@ -184,7 +216,12 @@ BatchLaunch launch_args(const esbgk_batch* b, int64_t n) {
   a.wpB = b->at(b->lay.wpB);
   a.lc = b->at(b->lay.lc);
   a.nsteps = n;
-  a.parity = b->parity;
+  a.red.level = reinterpret_cast<const int64_t*>(b->at(b->lay.level));
+  a.red.R = b->R;
+  a.red.uprev = b->at(b->lay.uprev);
+  a.red.chunks = reinterpret_cast<double*>(b->at(b->lay.chunks));
+  a.red.out = reinterpret_cast<double*>(b->at(b->lay.red_out));
+  a.red.red_level = reinterpret_cast<int64_t*>(b->at(b->lay.red_level));
   a.nbins = b->nbins;
   a.threads = b->threads;
   a.stream = b->stream;
@@ -238,6 +275,100 @@ int rest_state(esbgk_batch* b, const double* noise, double amp) {
   return ESBGK_OK;
 }
 
+// Device step counter = the host's, no reduction recorded yet.
+int reset_levels(esbgk_batch* b) {
+  BHIP(b, hipMemcpyAsync(b->at(b->lay.level), &b->steps, sizeof(int64_t), hipMemcpyHostToDevice, b->stream),
+       "batch level");
+  BHIP(b, hipMemsetAsync(b->at(b->lay.red_level), 0xff, b->p.size() * sizeof(int64_t), b->stream), "batch level");
+  BHIP(b, hipStreamSynchronize(b->stream), "batch level");
+  return ESBGK_OK;
+}
+
+// Release the captured launches; a replay may still be queued on the
+// caller's stream, so wait for it first.
+void drop_batch_graphs(esbgk_batch* b) {
+  if (!b->graphs.empty() && hipStreamSynchronize(b->stream) != hipSuccess) {
+    b->sticky = ESBGK_E_HIP;
+    b->err = "synchronize before releasing the batch graphs failed";
+  }
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
+  b->graphs.clear();
+}
+
+// The captured launch of n steps (kernel + level update), built on first use.
+int batch_graph(esbgk_batch* b, int64_t n, hipGraphExec_t* out) {
+  for (auto& g : b->graphs)
+    if (g.first == n) {
+      *out = g.second;
+      return ESBGK_OK;
+    }
+  if (!b->cap) {
+    hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      b->cap = nullptr;
+      return bfail(b, e, "create capture stream");
+    }
+  }
+  if (b->graphs.size() >= 4) drop_batch_graphs(b);   // a few step counts in use at a time
+  BHIP(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "begin capture");
+  BatchLaunch a = launch_args(b, n);
+  a.stream = b->cap;
+  const hipError_t le = launch_batch(b->velset, b->storage, a);
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(b->cap, &g);
+  if (le != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return bfail(b, le, "capture batch step");
+  }
+  if (ee != hipSuccess) return bfail(b, ee, "end capture");
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) return bfail(b, ie, "instantiate batch graph");
+  b->graphs.push_back({n, ex});
+  *out = ex;
+  return ESBGK_OK;
+}
+
+// Host form of the raw sums of one problem (as esbgk_reduce): mass, energy,
+// momentum, mass flow rate dx^(D-1)/nx sum rho u_x, residual, level.
+bool finish_reduction(const esbgk_batch* b, int i, const double* raw, int64_t level, double* out) {
+  const esbgk_shape& s = b->p[i].shape;
+  const int D = b->lat->D;
+  const int nref = s.n_ref > 0 ? s.n_ref : (D == 2 ? s.ny : s.nz);
+  const double dx = 1.0 / double(nref);
+  for (int k = 0; k < 5; ++k) out[k] = raw[k];
+  out[5] = std::pow(dx, D - 1) / double(s.nx) * raw[2];
+  out[6] = raw[6] > 0.0 ? std::sqrt(raw[5] / raw[6]) : 0.0;
+  out[7] = double(level);
+  return raw[7] == 0.0 && std::isfinite(raw[0]) && std::isfinite(raw[1]);
+}
+
+int fetch_batch_reduction(esbgk_batch* b, double* out) {
+  const size_t n = b->p.size();
+  std::vector<double> raw(n * NRED);
+  std::vector<int64_t> lev(n);
+  BHIP(b, hipMemcpyAsync(raw.data(), b->at(b->lay.red_out), raw.size() * 8, hipMemcpyDeviceToHost, b->stream),
+       "batch reduction");
+  BHIP(b, hipMemcpyAsync(lev.data(), b->at(b->lay.red_level), n * 8, hipMemcpyDeviceToHost, b->stream),
+       "batch reduction");
+  BHIP(b, hipStreamSynchronize(b->stream), "batch reduction");
+  bool ok = true;
+  for (size_t i = 0; i < n; ++i) {
+    if (lev[i] < 0) {
+      b->err = "no reduction has run since the state was set";
+      return ESBGK_E_STATE;
+    }
+    ok = finish_reduction(b, int(i), raw.data() + i * NRED, lev[i], out + i * 8) && ok;
+  }
+  if (!ok) {
+    b->sticky = ESBGK_E_NONFINITE;
+    b->err = "reduction found a non-finite value, rho <= 0 or T <= 0";
+    return ESBGK_E_NONFINITE;
+  }
+  return ESBGK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -255,8 +386,11 @@ int esbgk_batch_create(const esbgk_problem* problems, int n, void* d_workspace, 
   if (!out) return ESBGK_E_INVALID;
   *out = nullptr;
   if (!problems || n < 1) return ESBGK_E_INVALID;
-  for (int i = 0; i < n; ++i)
-    if (!valid_problem(problems[i], problems[0], nullptr)) return ESBGK_E_INVALID;
+  for (int i = 0; i < n; ++i) {
+    std::string why;
+    if (!valid_problem(problems[i], problems[0], &why))
+      return why == UNSTABLE_MSG ? ESBGK_E_UNSTABLE : ESBGK_E_INVALID;
+  }
   const HostLattice* lat = host_lattice(problems[0].shape.velset);
   if (!lat) return ESBGK_E_INVALID;
   const BLayout lay = blayout(problems, n);
@@ -278,7 +412,7 @@ int esbgk_batch_create(const esbgk_problem* problems, int n, void* d_workspace, 
   }
   b->cus = prop.multiProcessorCount;
   // descriptors and parameter blocks
-  size_t pop = 0, wp = 0;
+  size_t pop = 0, wp = 0, cell0 = 0, chunk0 = 0;
   b->bp.resize(n);
   const size_t ppsz = csize(b->storage) == 8 ? sizeof(ProbParams<double>) : sizeof(ProbParams<float>);
   std::vector<unsigned char> pps(size_t(n) * ppsz);
@@ -290,6 +424,10 @@ int esbgk_batch_create(const esbgk_problem* problems, int n, void* d_workspace, 
                   q.geo);
     q.pop_off = pop;
     q.wp_off = uint32_t(wp);
+    q.cell_off = cell0;
+    q.chunk_off = uint32_t(chunk0);
+    cell0 += q.geo.ncells;
+    chunk0 += (q.geo.ncells + 63u) / 64u;
     pop += size_t(lat->Q) * q.geo.ncells;
     pop = (pop + 63) / 64 * 64;
     wp += 6 * size_t(q.geo.ncols);
@@ -338,6 +476,8 @@ int esbgk_batch_create(const esbgk_problem* problems, int n, void* d_workspace, 
 
 int esbgk_batch_destroy(esbgk_batch* b) {
   if (!b) return ESBGK_E_INVALID;
+  drop_batch_graphs(b);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
   delete b;
   return ESBGK_OK;
 }
@@ -349,6 +489,7 @@ int esbgk_batch_set_layout(esbgk_batch* b, int threads, int nbins) {
     b->err = "threads must be a multiple of 64 up to the storage type's limit; nbins >= 1";
     return ESBGK_E_INVALID;
   }
+  drop_batch_graphs(b);
   b->threads = uint32_t(threads);
   return build_bins(b, uint32_t(nbins));
 }
@@ -368,23 +509,30 @@ int esbgk_batch_autotune(esbgk_batch* b, int steps_per_trial) {
     return ESBGK_E_INVALID;
   }
   // trials run on the uniform rest state; the state must be set afterwards
+  drop_batch_graphs(b);
   b->parity = 0;
+  b->steps = 0;
   int rc = rest_state(b, nullptr, 0.0);
+  if (rc) return rc;
+  rc = reset_levels(b);
   if (rc) return rc;
   b->state_set = false;
   const int maxt = batch_max_threads(ssize(b->storage));
+  // candidate bin counts: 1, 2, 4, 8 workgroups per compute unit, and one
+  // problem per workgroup
+  std::vector<uint32_t> bins_c;
+  for (int per : {1, 2, 4, 8}) bins_c.push_back(uint32_t(b->cus) * uint32_t(per));
+  bins_c.push_back(uint32_t(b->p.size()));
   hipEvent_t e0, e1;
   BHIP(b, hipEventCreate(&e0), "autotune");
   BHIP(b, hipEventCreate(&e1), "autotune");
   float best = 1e30f;
   uint32_t best_t = b->threads, best_n = b->nbins;
   for (int t = 256; t <= maxt; t *= 2) {
-    for (int per : {1, 2, 4, 8}) {
-      const uint32_t nb = uint32_t(b->cus) * uint32_t(per);
+    for (uint32_t nb : bins_c) {
       b->threads = uint32_t(t);
       if (build_bins(b, nb) != ESBGK_OK) continue;
       BatchLaunch a = launch_args(b, 2);
-      a.parity = 0;
       BHIP(b, launch_batch(b->velset, b->storage, a), "autotune");
       a.nsteps = steps_per_trial;
       BHIP(b, hipEventRecord(e0, b->stream), "autotune");
@@ -403,7 +551,9 @@ int esbgk_batch_autotune(esbgk_batch* b, int steps_per_trial) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->threads = best_t;
-  return build_bins(b, best_n);
+  rc = build_bins(b, best_n);
+  if (rc) return rc;
+  return reset_levels(b);
 }
 
 int esbgk_batch_init_equilibrium(esbgk_batch* b, const double* noise, double amplitude) {
@@ -415,7 +565,7 @@ int esbgk_batch_init_equilibrium(esbgk_batch* b, const double* noise, double amp
   if (rc) return rc;
   b->state_set = true;
   b->steps = 0;
-  return ESBGK_OK;
+  return reset_levels(b);
 }
 
 int esbgk_batch_step(esbgk_batch* b, int64_t n) {
@@ -427,10 +577,77 @@ int esbgk_batch_step(esbgk_batch* b, int64_t n) {
     return ESBGK_E_STATE;
   }
   if (n == 0) return ESBGK_OK;
-  BatchLaunch a = launch_args(b, n);
-  BHIP(b, launch_batch(b->velset, b->storage, a), "batch step");
+  if (b->use_graphs) {
+    hipGraphExec_t g = nullptr;
+    const int rc = batch_graph(b, n, &g);
+    if (rc) return rc;
+    BHIP(b, hipGraphLaunch(g, b->stream), "batch graph launch");
+  } else {
+    BatchLaunch a = launch_args(b, n);
+    BHIP(b, launch_batch(b->velset, b->storage, a), "batch step");
+  }
   b->parity ^= int(n & 1);
   b->steps += n;
+  return ESBGK_OK;
+}
+
+int esbgk_batch_use_graphs(esbgk_batch* b, int on) {
+  if (!b) return ESBGK_E_INVALID;
+  if (b->sticky) return b->sticky;
+  if (on != 0 && on != 1) {
+    b->err = "on must be 0 or 1";
+    return ESBGK_E_INVALID;
+  }
+  if (!on) drop_batch_graphs(b);
+  b->use_graphs = on != 0;
+  return ESBGK_OK;
+}
+
+int esbgk_batch_set_reduce_interval(esbgk_batch* b, int64_t R) {
+  if (!b) return ESBGK_E_INVALID;
+  if (b->sticky) return b->sticky;
+  if (R < 0) {
+    b->err = "R must be >= 0";
+    return ESBGK_E_INVALID;
+  }
+  if (R != b->R) drop_batch_graphs(b);   // R is baked into the captured launches
+  b->R = R;
+  return ESBGK_OK;
+}
+
+int esbgk_batch_reduce(esbgk_batch* b, double* out) {
+  if (!b || !out) return ESBGK_E_INVALID;
+  if (b->sticky) return b->sticky;
+  if (!b->state_set) {
+    b->err = "no state set";
+    return ESBGK_E_STATE;
+  }
+  BatchLaunch a = launch_args(b, 0);
+  BHIP(b, launch_batch_reduce(b->velset, b->storage, a, b->at(b->lay.pps64), b->at(b->lay.lc64), b->steps),
+       "batch reduce");
+  return fetch_batch_reduction(b, out);
+}
+
+int esbgk_batch_last_reduction(esbgk_batch* b, double* out) {
+  if (!b || !out) return ESBGK_E_INVALID;
+  if (b->sticky) return b->sticky;
+  if (!b->state_set) {
+    b->err = "no state set";
+    return ESBGK_E_STATE;
+  }
+  return fetch_batch_reduction(b, out);
+}
+
+int esbgk_batch_layout_info(const esbgk_batch* b, int* max_problems_per_bin, int64_t* max_cells_per_thread) {
+  if (!b) return ESBGK_E_INVALID;
+  int mp = 0;
+  int64_t mc = 0;
+  for (size_t k = 0; k < b->bin_slots.size(); ++k) {
+    mp = std::max(mp, int(b->bin_count[k]));
+    mc = std::max<int64_t>(mc, (int64_t(b->bin_slots[k]) + b->threads - 1) / b->threads);
+  }
+  if (max_problems_per_bin) *max_problems_per_bin = mp;
+  if (max_cells_per_thread) *max_cells_per_thread = mc;
   return ESBGK_OK;
 }
 

@@ -9,10 +9,6 @@
 
 namespace esbgk {
 
-// FP64 reduction slots: mass, energy, momentum x/y/z, sum |u - u_prev|^2,
-// sum |u|^2, number of invalid cells.
-constexpr int NRED = 8;
-
 struct StepArgs {
   Geometry geo;
   const void* src;      // populations read (storage type)
@@ -26,6 +22,7 @@ struct StepArgs {
   void* uprev;          // [D][ncells] velocity of the previous reduction (compute type)
   int have_prev;
   int reduce;           // step kernel: fuse the reductions
+  int rev;              // step kernel: walk the tiles in reverse order
   double* red_part;     // [workgroups][NRED]
   hipStream_t stream;
 };
@@ -40,6 +37,7 @@ hipError_t launch_moments(int velset, int storage, const StepArgs& a, uint32_t c
 hipError_t launch_init(int velset, int storage, const StepArgs& a, double r, const double* rho, const double* u,
                        const double* T, const double* noise, double amp, uint32_t c0, uint32_t count);
 hipError_t launch_wall_partials(int velset, int storage, const StepArgs& a);
+
 // Rebuild the wall tables of pp64 (and of pp32 when not null) for the step
 // from the level held in *level; advance: then increment *level.
 hipError_t launch_wall_tables(int velset, const WallProgram* prog, const void* lc64, void* pp64, void* pp32,

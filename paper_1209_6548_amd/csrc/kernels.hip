@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "reduce.h"
 #include "stream.h"
 
 namespace esbgk {
@@ -37,12 +38,6 @@ namespace esbgk {
 constexpr int BLOCK = 256;
 
 // ---- FP64 reductions ---------------------------------------------------------
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // Sum NRED values over the workgroup (fixed order) and write them to out.
 __device__ __forceinline__ void block_reduce_write(double (&v)[NRED], double* __restrict__ out) {
@@ -60,36 +55,6 @@ __device__ __forceinline__ void block_reduce_write(double (&v)[NRED], double* __
     for (int w = 0; w < BLOCK / 64; ++w) s += lds[w][threadIdx.x];
     out[threadIdx.x] = s;
   }
-}
-
-// Per-cell contributions: mass, energy, momentum (3), |u - u_prev|^2, |u|^2,
-// invalid-cell count. rho and T are formed in FP64 from their deviations.
-template <class L, typename C, typename U>
-__device__ __forceinline__ void cell_contrib(const CellState<L, C>& s, U* __restrict__ uprev, uint32_t cell,
-                                             uint32_t ncells, int have_prev, double (&v)[NRED]) {
-  constexpr int D = L::D;
-  const double rho = 1.0 + double(s.drho);
-  const double T = 1.0 + double(s.theta);
-  double uu = 0.0, du = 0.0;
-  v[0] = rho;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) v[2 + i] = 0.0;
-#pragma unroll
-  for (int i = 0; i < D; ++i) {
-    const double ui = double(s.u[i]);
-    v[2 + i] = rho * ui;
-    uu += ui * ui;
-    if (uprev) {
-      const double up = have_prev ? double(uprev[size_t(i) * ncells + cell]) : ui;
-      du += (ui - up) * (ui - up);
-      uprev[size_t(i) * ncells + cell] = U(ui);
-    }
-  }
-  v[1] = 0.5 * (rho * uu + rho * D * T);
-  v[5] = du;
-  v[6] = uu;
-  const bool bad = !(rho > 0.0) || !(T > 0.0) || !(uu < 1e300) || !(v[1] < 1e300);
-  v[7] = bad ? 1.0 : 0.0;
 }
 
 // ---- kernels ---------------------------------------------------------------
@@ -117,9 +82,9 @@ __global__ void __launch_bounds__(BLOCK)
 k_step(Geometry geo, const S* __restrict__ src, S* __restrict__ dst, const typename StepT<S>::type* __restrict__ wp_src,
        typename StepT<S>::type* __restrict__ wp_dst, const LatConsts<typename StepT<S>::type>* __restrict__ lc,
        const ProbParams<typename StepT<S>::type>* __restrict__ pp, typename StepT<S>::type* __restrict__ uprev,
-       int have_prev, double* __restrict__ red_part) {
+       int have_prev, double* __restrict__ red_part, int rev) {
   using C = typename StepT<S>::type;
-  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t blk = tile_of(blockIdx.x, gridDim.x, rev);
   const Slot sl = slot_of(blk, geo);
   double v[NRED];
   if (REDUCE) {
@@ -343,12 +308,13 @@ static hipError_t step_t(const StepArgs& a) {
     hipLaunchKernelGGL((k_step<L, S, true>), dim3(nb), dim3(BLOCK), 0, a.stream, a.geo, static_cast<const S*>(a.src),
                        static_cast<S*>(a.dst), static_cast<const C*>(a.wp_src), static_cast<C*>(a.wp_dst),
                        static_cast<const LatConsts<C>*>(a.lc), static_cast<const ProbParams<C>*>(a.pp),
-                       static_cast<C*>(a.uprev), a.have_prev, a.red_part);
+                       static_cast<C*>(a.uprev), a.have_prev, a.red_part, a.rev);
   } else {
     hipLaunchKernelGGL((k_step<L, S, false>), dim3(nb), dim3(BLOCK), 0, a.stream, a.geo,
                        static_cast<const S*>(a.src), static_cast<S*>(a.dst), static_cast<const C*>(a.wp_src),
                        static_cast<C*>(a.wp_dst), static_cast<const LatConsts<C>*>(a.lc),
-                       static_cast<const ProbParams<C>*>(a.pp), static_cast<C*>(a.uprev), a.have_prev, a.red_part);
+                       static_cast<const ProbParams<C>*>(a.pp), static_cast<C*>(a.uprev), a.have_prev, a.red_part,
+                       a.rev);
   }
   return hipGetLastError();
 }

@@ -93,6 +93,10 @@ struct Geometry {
   uint32_t window_ok;        // 7 slice blocks span < 4 GiB (32-bit offsets of the wave pull)
 };
 
+// FP64 reduction slots: mass, energy, momentum x/y/z, sum |u - u_prev|^2,
+// sum |u|^2, number of invalid cells.
+constexpr int NRED = 8;
+
 // Fields per cell returned by the moments kernel: rho, u[D], T, sigma, q[D].
 constexpr int nfields(int D) { return D == 2 ? 9 : 14; }
 

@@ -43,6 +43,17 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
   return b;
 }
 
+// Tile of workgroup b for a launch that walks the tiles forward (rev = 0) or
+// backward (rev = 1). Consecutive steps of a ping-pong pair alternate: the
+// tiles a step wrote last are then the first its successor reads, while they
+// are still held by the memory-side cache (256 MB on MI355X) - the reuse
+// distance of the populations a step writes falls from a whole step's
+// traffic to twice what remains of it after the tile.
+__device__ __forceinline__ uint32_t tile_of(uint32_t b, uint32_t nb, int rev) {
+  const uint32_t t = xcd_block(b, nb);
+  return rev ? nb - 1u - t : t;
+}
+
 __device__ __forceinline__ int wrapc(int v, int n) {
   // v in [-3, n + 2], n >= 1
   if (v < 0) v += n;

@@ -435,6 +435,17 @@ int esbgk_tvd_destroy(esbgk_tvd* c) {
 
 double esbgk_tvd_time_step(const esbgk_tvd* c) { return c ? c->dt : 0.0; }
 
+int esbgk_tvd_bounded(int velset, int n_ref, double cfl, double Kn, double Pr, int axes) {
+  SetTab t;
+  if (!set_tab(velset, t)) return ESBGK_E_INVALID;
+  if (n_ref < 1 || !(cfl > 0.0 && cfl <= 1.0) || !(Kn > 0.0) || !std::isfinite(Kn) ||
+      !(Pr >= 2.0 / 3.0 - 1e-12) || !std::isfinite(Pr) || axes < 1 || axes > t.D)
+    return ESBGK_E_INVALID;
+  const double dt = cfl / (double(n_ref) * t.cmax);
+  const double w = dt * Pr / Kn;   // dt/tau at rho = T = 1
+  return double(axes) * cfl <= 1.0 - w ? ESBGK_OK : ESBGK_E_UNSTABLE;
+}
+
 int esbgk_tvd_set_gas(esbgk_tvd* c, double Kn, double Pr, double varpi) {
   TVD_CHECK(c);
   if (!(Kn > 0.0) || !std::isfinite(Kn)) return tset_err(c, ESBGK_E_INVALID, "Kn must be > 0");

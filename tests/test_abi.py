@@ -146,3 +146,51 @@ def test_tvd_create_rejects_missing_workspace_and_bad_cfl():
     assert not t.value
     assert lib.esbgk_tvd_create(ctypes.byref(s), 1.5, None, 0, None, ctypes.byref(t)) == B.E_INVALID
     assert b"cfl" in lib.esbgk_tvd_last_error(None)
+
+
+def test_tvd_bound_check_on_host():
+    """esbgk_tvd_bounded: axes * cfl <= 1 - dt/tau at rho = T = 1, with
+    dt = cfl / (n_ref max|c|) and tau = Kn/Pr (no GPU needed)."""
+    from paper_1209_6548_amd import binding as B
+    cmax = float(np.max(np.abs(B.tvd_velocity_set("D2Q36GH")[0])))
+    n_ref, Kn, Pr = 11, 0.05, 2 / 3
+    w = lambda cfl: cfl / (n_ref * cmax) * Pr / Kn   # noqa: E731
+    assert B.tvd_bounded("D2Q36GH", n_ref, 0.4, Kn, Pr, 2) == B.OK
+    assert 2 * 0.4 <= 1 - w(0.4)
+    assert B.tvd_bounded("D2Q36GH", n_ref, 0.5, Kn, Pr, 2) == B.E_UNSTABLE
+    assert 2 * 0.5 > 1 - w(0.5)
+    assert B.tvd_bounded("D2Q36GH", n_ref, 0.5, Kn, Pr, 1) == B.OK
+    # the defaults of TVDLattice sum the Courant numbers of every axis to 0.9
+    assert B.default_tvd_cfl(2) == 0.45 and B.default_tvd_cfl(3) == 0.3
+    assert B.tvd_bounded("D2Q36GH", 1024, B.default_tvd_cfl(2), 0.05, 2 / 3, 2) == B.OK
+    assert B.tvd_bounded("D3Q216GH", 128, B.default_tvd_cfl(3), 0.05, 2 / 3, 3) == B.OK
+    # a collision weight of 0.15 leaves 0.85 for the advection: 0.9 is too much there
+    assert B.tvd_bounded("D3Q216GH", 8, 0.3, 0.05, 2 / 3, 3) == B.E_UNSTABLE
+    for bad in ((0, 0.3, 0.05, 2 / 3, 2), (11, 1.5, 0.05, 2 / 3, 2), (11, 0.3, 0.0, 2 / 3, 2),
+                (11, 0.3, 0.05, 0.5, 2), (11, 0.3, 0.05, 2 / 3, 3)):
+        assert B.tvd_bounded("D2Q36GH", *bad) == B.E_INVALID
+
+
+def test_batch_rejects_unstable_euler_problem():
+    """A batched Euler problem with dt/tau >= 2 at rho = T = 1 is rejected like
+    esbgk_set_gas rejects it (workspace size 0); the trapezoidal rule takes
+    it."""
+    import ctypes
+
+    from paper_1209_6548_amd import binding as B
+    r = B.lattice_info("D2Q37")["r"]
+    ny = 16
+    dt = 1.0 / (ny * r)
+
+    def prob(scheme, Kn, Pr):
+        p = B.Problem()
+        p.shape = B.Shape(B.D2Q37, 4, ny, 1, 1, B.F32, scheme, 0)
+        p.Kn, p.Pr, p.varpi = Kn, Pr, 0.5
+        p.T_w[0] = p.T_w[1] = 1.0
+        return p
+
+    L = B.lib()
+    for scheme, Kn, Pr, ok in ((B.EULER, dt / 1.9, 1.0, True), (B.EULER, dt / 2.1, 1.0, False),
+                               (B.EULER, dt / 2.1 * 0.9, 0.9, False), (B.TRAPEZOID, dt / 2.1, 1.0, True)):
+        arr = (B.Problem * 1)(prob(scheme, Kn, Pr))
+        assert (L.esbgk_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), 1) > 0) == ok

@@ -76,3 +76,44 @@ def test_one_cell_tvd_fp64():
     f = OF.run(f, prob, 6)
     h, ho = lat.get_populations(), f / gh.w[:, None] - 1.0
     assert np.abs(h - ho).max() / np.abs(ho).max() < 1e-12
+
+
+def test_graph_release_waits_for_queued_replays():
+    """esbgk_step returns as soon as its graph replays are queued. Changing the
+    graph length, switching unsteady heating on and destroying the handle
+    release the captured graphs; they first wait for the stream, so the
+    queued replays finish. The state then equals direct launches bit for
+    bit, and a fresh handle steps normally afterwards."""
+    cfg = H.small_cfg("D2Q37", (200, 64), True)
+    rho, u, T, xi, amp = H.init_fields(cfg, 200 * 64, 2, 37, seed=9)
+
+    def fresh():
+        lat = H.gpu_lattice(cfg, "f32")
+        lat.init_equilibrium(rho, u, T, xi, amp)
+        return lat
+
+    ref = fresh()
+    ref.set_graph_steps(0)
+    ref.step(160)
+    h_ref = ref.get_populations()
+    ref.close()
+
+    lat = fresh()
+    lat.step(64)               # two replays of the 32-step graph, queued
+    lat.set_graph_steps(16)    # releases both graphs
+    lat.step(32)
+    lat.set_graph_steps(32)
+    lat.step(64)
+    assert lat.steps_done == 160
+    np.testing.assert_array_equal(lat.get_populations(), h_ref)
+
+    lat.step(64)
+    lat.set_heating(1, 0.01, 3.0)   # heating on: the graphs are captured again with the table rebuilds
+    lat.set_heating(1, 0.0, 0.0)
+    lat.step(32)
+    lat.close()                      # replays still queued
+
+    again = fresh()
+    again.set_graph_steps(0)
+    again.step(160)
+    np.testing.assert_array_equal(again.get_populations(), h_ref)
