@@ -197,6 +197,20 @@ int esbgk_read_moments(esbgk_ctx* ctx, double* h_out, int* F);
  * T <= 0. */
 int esbgk_reduce(esbgk_ctx* ctx, double out[8]);
 
+/* For callers that cannot allocate device memory: esbgk_reduce without the
+ * handle's workspace scratch. The per-workgroup partials (at most 1024
+ * workgroups, each folding every 1024th block of 256 cells in a fixed order)
+ * and the 8 final sums live in a static device array of the library
+ * (1024 * 8 + 8 doubles, about 64 KiB per GPU, held until the process ends;
+ * its address is looked up once per GPU, with that GPU current). Every
+ * lattice a handle accepts fits. Same results as esbgk_reduce up to the
+ * order of the FP64 additions (the cells are grouped differently); it also
+ * becomes the handle's latest reduction and u_prev, as esbgk_reduce does.
+ * Calls no allocation routine. All calls on one GPU share the array:
+ * calls that overlap in time on one GPU (other streams, other threads) race;
+ * serialise them. Synchronises the handle's stream. */
+int esbgk_reduce_noalloc(esbgk_ctx* ctx, double out[8]);
+
 /* R > 0: fuse the reductions into every R-th step (R = 0 disables);
  * esbgk_last_reduction returns the latest such result. */
 int esbgk_set_reduce_interval(esbgk_ctx* ctx, int64_t R);

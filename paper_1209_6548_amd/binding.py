@@ -82,6 +82,7 @@ def lib():
             "esbgk_set_graph_steps": (I, [P, I]),
             "esbgk_read_moments": (I, [P, DP, P]),
             "esbgk_reduce": (I, [P, DP]),
+            "esbgk_reduce_noalloc": (I, [P, DP]),
             "esbgk_set_reduce_interval": (I, [P, I64]),
             "esbgk_last_reduction": (I, [P, DP]),
             "esbgk_steps_done": (I64, [P]),
@@ -299,6 +300,12 @@ class Lattice:
     def reduce(self):
         out = np.empty(8)
         self._check(lib().esbgk_reduce(self._ctx, _dp(out)), "reduce")
+        return self._red(out)
+
+    def reduce_noalloc(self):
+        """esbgk_reduce_noalloc: the same reductions with no workspace scratch."""
+        out = np.empty(8)
+        self._check(lib().esbgk_reduce_noalloc(self._ctx, _dp(out)), "reduce_noalloc")
         return self._red(out)
 
     def set_reduce_interval(self, R):

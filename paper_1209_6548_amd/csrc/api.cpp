@@ -111,6 +111,7 @@ struct esbgk_ctx {
   Layout lay{};
   char* ws = nullptr;
   hipStream_t stream = nullptr;
+  int device = 0;                 // the GPU current at creation
   int cur = 0;                    // buffer holding the current state
   bool state_set = false;
   int64_t steps = 0;
@@ -367,6 +368,11 @@ int esbgk_create(const esbgk_shape* shape, void* d_workspace, size_t ws_bytes, v
   c->lay = lay;
   c->ws = static_cast<char*>(d_workspace);
   c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    g_create_error = "create: no current device";
+    delete c;
+    return ESBGK_E_HIP;
+  }
   c->n_ref = shape->n_ref > 0 ? shape->n_ref : (shape->walls ? (lat->D == 2 ? shape->ny : shape->nz) : shape->nx);
   c->geo = geometry_of(shape);
   pack_lattice<double>(*lat, c->lc64);
@@ -724,6 +730,23 @@ int esbgk_reduce(esbgk_ctx* c, double out[8]) {
   HIP_OR_FAIL(c, launch_reduce(c->shape.velset, c->shape.storage, a), "reduce");
   HIP_OR_FAIL(c, launch_reduce_finalize(a.red_part, nblocks, reinterpret_cast<double*>(c->at(c->lay.red_out)),
                                         c->stream), "reduce");
+  c->have_prev = 1;
+  c->last_red_step = c->steps;
+  return fetch_reduction(c, out, c->steps);
+}
+
+int esbgk_reduce_noalloc(esbgk_ctx* c, double out[8]) {
+  CHECK_CTX(c);
+  if (!out) return set_err(c, ESBGK_E_INVALID, "out is null");
+  if (!c->state_set) return set_err(c, ESBGK_E_STATE, "no state set");
+  double* scr = nullptr;
+  HIP_OR_FAIL(c, noalloc_scratch(c->device, &scr), "scratch address");
+  StepArgs a = base_args(c);
+  if (c->heating()) HIP_OR_FAIL(c, wall_tables(c, 0, c->stream), "wall tables");
+  HIP_OR_FAIL(c, launch_reduce_noalloc(c->shape.velset, c->shape.storage, a, scr), "reduce");
+  // the sums become the handle's latest reduction, as with esbgk_reduce
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->at(c->lay.red_out), scr + size_t(NOALLOC_PARTS) * NRED, NRED * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream), "reduce");
   c->have_prev = 1;
   c->last_red_step = c->steps;
   return fetch_reduction(c, out, c->steps);

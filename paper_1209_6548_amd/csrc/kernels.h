@@ -38,6 +38,14 @@ hipError_t launch_init(int velset, int storage, const StepArgs& a, double r, con
                        const double* T, const double* noise, double amp, uint32_t c0, uint32_t count);
 hipError_t launch_wall_partials(int velset, int storage, const StepArgs& a);
 
+// Reductions that use no workspace: the partials of at most NOALLOC_PARTS
+// workgroups and the NRED sums live in a static device array of
+// kernels.hip (one per GPU). noalloc_scratch gives that GPU's address
+// (looked up once per device with the device current); the sums land at
+// scr + NOALLOC_PARTS * NRED.
+constexpr int NOALLOC_PARTS = 1024;
+hipError_t noalloc_scratch(int device, double** scr);
+hipError_t launch_reduce_noalloc(int velset, int storage, const StepArgs& a, double* scr);
 // Rebuild the wall tables of pp64 (and of pp32 when not null) for the step
 // from the level held in *level; advance: then increment *level.
 hipError_t launch_wall_tables(int velset, const WallProgram* prog, const void* lc64, void* pp64, void* pp32,

@@ -29,6 +29,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "kernels.h"
 #include "reduce.h"
 #include "stream.h"
@@ -134,6 +136,38 @@ k_reduce(Geometry geo, const S* __restrict__ src, const typename StepT<S>::type*
     cell_contrib<L, double, P>(st, uprev, sl.s * geo.inner + sl.i, geo.ncells, have_prev, v);
   }
   block_reduce_write(v, red_part + size_t(blk) * NRED);
+}
+
+// The same reductions folded onto at most gridDim.x workgroups: workgroup g
+// adds the cells of slot blocks g, g + gridDim.x, ... in that order, so the
+// partials need room for gridDim.x workgroups whatever the lattice size.
+template <class L, typename S>
+__global__ void __launch_bounds__(BLOCK)
+k_reduce_fold(Geometry geo, const S* __restrict__ src, const typename StepT<S>::type* __restrict__ wp,
+              const LatConsts<double>* __restrict__ lc, const ProbParams<double>* __restrict__ pp,
+              typename StepT<S>::type* __restrict__ uprev, int have_prev, uint32_t nblocks,
+              double* __restrict__ part) {
+  using P = typename StepT<S>::type;
+  double acc[NRED];
+#pragma unroll
+  for (int k = 0; k < NRED; ++k) acc[k] = 0.0;
+  for (uint32_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    const Slot sl = slot_of(blk, geo);
+    if (!sl.active) continue;
+    const CellPos p = slice_pos<L>(sl.s, sl.i, geo);
+    const PullMode mode = pull_mode_wave<L>(sl.s, p, geo);
+    double h[L::Q];
+    gather_wave<L, S, double, P>(h, src, geo, sl.s, sl.i, p, wp, pp, mode);
+    RawMoments<L, double> m;
+    raw_moments<L, double>(h, lc, false, m);
+    CellState<L, double> st;
+    reconstruct<L, double>(m, lc, pp, st);
+    double v[NRED];
+    cell_contrib<L, double, P>(st, uprev, sl.s * geo.inner + sl.i, geo.ncells, have_prev, v);
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) acc[k] += v[k];
+  }
+  block_reduce_write(acc, part + size_t(blockIdx.x) * NRED);
 }
 
 __global__ void __launch_bounds__(BLOCK) k_reduce_finalize(const double* __restrict__ part, uint32_t nparts,
@@ -381,6 +415,62 @@ hipError_t launch_step(int velset, int storage, const StepArgs& a) {
 
 hipError_t launch_reduce(int velset, int storage, const StepArgs& a) {
   ESBGK_DISPATCH(velset, storage, (reduce_t<L, S>(a)));
+}
+
+// ---- reductions without a workspace ----------------------------------------
+
+// Device memory of the workspace-free reduction: the partials of at most
+// NOALLOC_PARTS workgroups, then the NRED final sums. One copy per GPU,
+// shared by every call on that GPU, for the life of the process.
+static __device__ __align__(256) double scratch[NOALLOC_PARTS * NRED + NRED];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, double** out) {
+  *out = nullptr;
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) {
+      const hipError_t r = hipSetDevice(cur);
+      if (e == hipSuccess) e = r;
+    }
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch[device];
+  return hipSuccess;
+}
+
+template <class L, typename S>
+static hipError_t reduce_fold_t(const StepArgs& a, double* scr) {
+  using C = typename StepT<S>::type;
+  const uint32_t nb = slot_blocks(a.geo);
+  const uint32_t parts = nb < uint32_t(NOALLOC_PARTS) ? nb : uint32_t(NOALLOC_PARTS);
+  hipLaunchKernelGGL((k_reduce_fold<L, S>), dim3(parts), dim3(BLOCK), 0, a.stream, a.geo,
+                     static_cast<const S*>(a.src), static_cast<const C*>(a.wp_src),
+                     static_cast<const LatConsts<double>*>(a.lc64), static_cast<const ProbParams<double>*>(a.pp64),
+                     static_cast<C*>(a.uprev), a.have_prev, nb, scr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_finalize, dim3(1), dim3(BLOCK), 0, a.stream, scr, parts,
+                     scr + size_t(NOALLOC_PARTS) * NRED);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_noalloc(int velset, int storage, const StepArgs& a, double* scr) {
+  ESBGK_DISPATCH(velset, storage, (reduce_fold_t<L, S>(a, scr)));
 }
 
 hipError_t launch_reduce_finalize(const double* part, uint32_t nparts, double* out, hipStream_t stream) {
