@@ -35,6 +35,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_traffic_poiseuille1024.json")
+PAIR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair_traffic_poiseuille1024.json")
 TVD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tvd_traffic_periodic1024.json")
 
 
@@ -57,8 +58,16 @@ def make_lattice(cfg, storage):
 
 def time_steps(lat, steps, warmup):
     """Average step time (ms) from HIP events on the stream the kernels run on
-    (torch's current stream, which the binding hands to the library)."""
+    (torch's current stream, which the binding hands to the library). Before
+    the warmup steps, one untimed run of the graph length captures the step
+    graphs (of the lattice path; the TVD path launches directly), so that
+    their capture falls outside the timed region; an even K up to 64 is the
+    graph length itself (the timed steps are one replay)."""
     import torch
+    if hasattr(lat, "set_graph_steps"):
+        g = steps if steps % 2 == 0 and 2 <= steps <= 64 else 32
+        lat.set_graph_steps(g)
+        lat.step(g)
     lat.step(warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -70,14 +79,16 @@ def time_steps(lat, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def bench_single(cfg, storage, steps, warmup):
+def bench_single(cfg, storage, steps, warmup, inplace=2):
     lat = make_lattice(cfg, storage)
+    lat.set_inplace(inplace)
     ms = time_steps(lat, steps, warmup)
     cells = int(np.prod(cfg["dims"]))
     s = {"f64": 8, "f32": 4, "f16": 2}[storage]
     bytes_per_step = 2 * lat.Q * s * cells
     out = dict(storage=storage, ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6,
-               algorithmic_GBs=bytes_per_step / (ms * 1e-3) / 1e9, bytes_per_cell=2 * lat.Q * s)
+               algorithmic_GBs=bytes_per_step / (ms * 1e-3) / 1e9, bytes_per_cell=2 * lat.Q * s,
+               in_place_pairs=lat.inplace_active)
     red = lat.reduce()
     out["finite"] = bool(np.isfinite(red["mass"]) and np.isfinite(red["energy"]))
     lat.close()
@@ -158,8 +169,10 @@ def bench_batch(r, steps, warmup, fp64_sample=16):
                           T_w=s["T_w"], u_w=s["u_w"], g=s["g"]) for s in specs]
     cells = sum(s["dims"][0] * s["dims"][1] for s in specs)
     b = Batch(probs)
-    layout = b.autotune(20)
+    b.autotune(20)
+    info = b.layout_info()
     b.init_equilibrium()
+    b.set_reduce_interval(1000)      # the FP64 per-problem reductions ride along every 1000 steps
     b.step(warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -169,8 +182,11 @@ def bench_batch(r, steps, warmup, fp64_sample=16):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    out = dict(problems=len(specs), cells=cells, layout=dict(threads=layout[0], bins=layout[1]),
-               ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6)
+    red = b.last_reduction() if steps + warmup >= 1000 else b.reduce()
+    out = dict(problems=len(specs), cells=cells, layout=info, launch="one persistent kernel per step() call, "
+               "captured in a HIP graph and replayed", reductions="FP64 per problem, fused every 1000 steps",
+               ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6,
+               finite=bool(all(np.isfinite(x["mass"]) and np.isfinite(x["energy"]) for x in red)))
     b.close()
     # per-problem FP64 loop on a sample of the same problems (same per-step work)
     rng = np.random.default_rng(0)
@@ -248,11 +264,13 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(r, budget_s=20.0, one_core_s=8.0):
+def cpu_baseline(r, budget_s=20.0, all_threads_s=8.0):
     """The FP64 oracle on a bounded sample of the same workload: the 1024 x
     1024 channel's per-cell work (D2Q37, walls, force, N = 4) on a 256 x 256
-    instance with the same Kn, Pr and walls, stepped until the time budget;
-    then again on one core (BLAS limited to one thread) for a shorter budget."""
+    instance with the same Kn, Pr and walls, stepped until the time budget on
+    one core (numpy with its BLAS limited to one thread: the oracle's array
+    operations do not run faster with more BLAS threads); then, for
+    comparison, with numpy's default thread pools for a shorter budget."""
     from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import lattice as OL
@@ -274,18 +292,19 @@ def cpu_baseline(r, budget_s=20.0, one_core_s=8.0):
             n += 1
         return n, time.perf_counter() - t0
 
-    n, dt = timed(budget_s)
-    threads = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
     with threadpool_limits(limits=1):
-        n1, dt1 = timed(one_core_s)
+        n, dt = timed(budget_s)
+    threads = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
+    nm, dtm = timed(all_threads_s)
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
         avail = os.cpu_count()
-    return dict(value=M * n / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
+    return dict(value=M * n / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
                 sample=f"256x256 D2Q37 channel (same Kn, Pr, walls, force as the 1024x1024 case), {n} steps in "
-                       f"{dt:.1f} s with numpy on {threads} BLAS threads",
-                one_core=dict(value=M * n1 / dt1 / 1e6, steps=n1, seconds=round(dt1, 2)),
+                       f"{dt:.1f} s on one core (numpy, BLAS limited to one thread)",
+                all_threads=dict(value=M * nm / dtm / 1e6, steps=nm, seconds=round(dtm, 2), blas_threads=threads,
+                                 note="numpy's default thread pools: no faster than one core for this oracle"),
                 host=dict(cpu_model=_cpu_model(), cores_available=avail))
 
 
@@ -321,6 +340,11 @@ def main():
         sys.exit(1)
     r = lattice_info("D2Q37")["r"]
     cfg = workloads.poiseuille_thermal_1024(r, storage=args.storage)
+    copy_gbs = None
+    if not args.profile:
+        # context for the roofline, measured first: it also brings the GPU out of idle
+        copy_gbs = copy_bandwidth()
+        log(f"device copy: {copy_gbs:.0f} GB/s")
     if args.profile:
         n = 1 << 28                                   # 2^28 floats = 1 GiB each way
         a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -340,6 +364,9 @@ def main():
     log(f"{args.storage}: {main_run['mlups']:.0f} MLUPS, {main_run['algorithmic_GBs']:.0f} GB/s")
     variants = {}
     if not args.only_main:
+        key = f"{args.storage}_two_buffers"
+        variants[key] = bench_single(cfg, args.storage, max(20, args.steps // 2), args.warmup, inplace=0)
+        log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
         for st in ("f64", "f16"):
             variants[st] = bench_single(cfg, st, max(20, args.steps // 2), args.warmup)
             log(f"{st}: {variants[st]['mlups']:.0f} MLUPS, {variants[st]['algorithmic_GBs']:.0f} GB/s")
@@ -382,10 +409,6 @@ def main():
         key = "periodic_gas_128x128x128_d3q216gh_f32"   # the paper's 3-D set
         variants[key] = bench_tvd("f32", max(5, args.steps // 20), 2, velset="D3Q216GH", dims=(128, 128, 128))
         log(f"{key}: {variants[key]['mlups']:.0f} MLUPS, {variants[key]['algorithmic_GBs']:.0f} GB/s")
-    copy_gbs = None
-    if not args.only_main:
-        copy_gbs = copy_bandwidth()
-        log(f"device copy: {copy_gbs:.0f} GB/s")
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")
@@ -393,7 +416,10 @@ def main():
         log(f"cpu: {cpu['value']:.3f} MLUPS")
     ms = main_run["ms_per_step"]
     achieved = main_run["algorithmic_GBs"]
-    traffic = measured_traffic(args.storage)
+    pairs = main_run["in_place_pairs"]
+    traffic = measured_traffic(args.storage, PAIR_TRAFFIC_FILE if pairs else TRAFFIC_FILE)
+    kernel = (f"k_pair<D2Q37, {args.storage}> (both steps of the in-place pair, one launch per step)" if pairs
+              else f"k_step<D2Q37, {args.storage}>")
     line = {
         "metric": "MLUPS", "value": round(main_run["mlups"], 1), "unit": "MLUPS",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
@@ -401,12 +427,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "velset": "D2Q37", "order_N": 4, "cells": 1024 * 1024,
                    "storage": f"{args.storage} deviational", "Kn": cfg["Kn"], "Pr": cfg["Pr"], "walls_T": list(cfg["T_w"]),
-                   "g_x_nondim": cfg["g"][0], "scheme": "trapezoid"},
+                   "g_x_nondim": cfg["g"][0], "scheme": "trapezoid", "in_place_pairs": pairs},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_over_algorithmic": (round(traffic / (main_run["bytes_per_cell"] * 1024 * 1024), 4)
                                                   if traffic else None),
-                     "kernel": f"k_step<D2Q37, {args.storage}>", "bytes_per_cell": main_run["bytes_per_cell"],
+                     "kernel": kernel, "bytes_per_cell": main_run["bytes_per_cell"],
                      "device_copy_GBs": round(copy_gbs, 1) if copy_gbs else None},
         "cpu_baseline": cpu,
         "variants": variants,

@@ -183,6 +183,24 @@ int esbgk_step(esbgk_ctx* ctx, int64_t n);
  * replay is queued or running when its graph is released. */
 int esbgk_set_graph_steps(esbgk_ctx* ctx, int steps);
 
+/* Pairs of steps in place, in one population buffer: the first step pulls
+ * (as above) and pushes each post-collision population to the slot of the
+ * opposite velocity at the cell it streams to, the only slot that no other
+ * cell touches; the second step reads those slots at its own cell and
+ * writes its populations back to their own slots, the layout the pair
+ * started from. Each cell's arithmetic is that of the two-buffer step, so
+ * the bits are the same; a run of pairs works on half the memory, which
+ * can then stay in the GPU's 256 MB memory-side cache. mode = 1: pairs;
+ * 0: always two buffers; 2 (default): pairs when the two buffers of one
+ * lattice exceed 256 MB and one buffer does not exceed 768 MB (where they
+ * were measured faster on MI355X). Pairs need a periodic lattice or fully
+ * diffuse walls (gamma = 1: a specular image would need the populations
+ * pushed across a wall); an odd remaining step uses two buffers. */
+int esbgk_set_inplace(esbgk_ctx* ctx, int mode);
+/* 1 if esbgk_step advances this handle in pairs (mode, walls and size as
+ * above), 0 if in two buffers; E_INVALID for a null handle. */
+int esbgk_inplace_active(const esbgk_ctx* ctx);
+
 /* Macroscopic fields of eq. mac at the current level, FP64 [F][cells] host:
  * rho, u[D], T, sigma (trace-free, components xx,xy,yy or
  * xx,xy,xz,yy,yz,zz), q[D]. F = 9 (2-D) or 14 (3-D); *F receives it. */

@@ -80,6 +80,8 @@ def lib():
             "esbgk_set_state": (I, [P, P, SZ]),
             "esbgk_step": (I, [P, I64]),
             "esbgk_set_graph_steps": (I, [P, I]),
+            "esbgk_set_inplace": (I, [P, I]),
+            "esbgk_inplace_active": (I, [P]),
             "esbgk_read_moments": (I, [P, DP, P]),
             "esbgk_reduce": (I, [P, DP]),
             "esbgk_reduce_noalloc": (I, [P, DP]),
@@ -276,6 +278,16 @@ class Lattice:
 
     def step(self, n=1):
         self._check(lib().esbgk_step(self._ctx, int(n)), "step")
+
+    def set_inplace(self, mode):
+        """esbgk_set_inplace: True / 1 pairs of steps in one buffer, False / 0
+        two buffers, 2 (default) pairs where they were measured faster."""
+        self._check(lib().esbgk_set_inplace(self._ctx, int(mode)), "set_inplace")
+
+    @property
+    def inplace_active(self):
+        """True when steps advance in in-place pairs (esbgk_inplace_active)."""
+        return lib().esbgk_inplace_active(self._ctx) == 1
 
     def set_graph_steps(self, steps):
         self._check(lib().esbgk_set_graph_steps(self._ctx, int(steps)), "set_graph_steps")

@@ -40,11 +40,12 @@ __device__ __forceinline__ void batch_cell(const BatchProblem& bp, uint32_t cell
   const CellPos p = cell_pos(cell, geo);
   C h[L::Q];
   gather_lane<L, S, C, C, uint32_t>(h, src, geo, p, wps, pp);
-  collide<L, C>(h, lc, pp, st);
+  S hs[L::Q];
+  collide_to<L, C, S>(h, hs, lc, pp, st);
   const uint32_t elem = uint32_t(cell_elem<L>(p, geo));
 #pragma unroll
-  for (int a = 0; a < L::Q; ++a) dst[a * geo.pstride + elem] = narrow<S, C>(h[a]);
-  write_wall_partials<L, S, C>([&](int a) { return narrow<S, C>(h[a]); }, p, geo, lc, wpd);
+  for (int a = 0; a < L::Q; ++a) dst[a * geo.pstride + elem] = hs[a];
+  write_wall_partials<L, S, C>([&](int a) { return hs[a]; }, p, geo, lc, wpd);
 }
 
 // Bin bookkeeping shared by the step and reduction kernels: the problems of

@@ -80,6 +80,15 @@ template <> __device__ __forceinline__ double pow_pos<double>(double x, double y
 // Storage conversions.
 template <typename C, typename S> __device__ __forceinline__ C widen(S v) { return C(v); }
 template <typename S, typename C> __device__ __forceinline__ S narrow(C v) { return S(v); }
+// FP32 -> FP16 storage: the FP32 value is rounded on its own (round to
+// nearest even). The empty asm keeps the compiler from folding the
+// conversion into the FMA that produced the value (a single rounding of the
+// exact result), which it would do in some kernels and not in others:
+// every path then stores the same bits.
+template <> __device__ __forceinline__ _Float16 narrow<_Float16, float>(float v) {
+  asm("" : "+v"(v));
+  return _Float16(v);
+}
 
 // ---- raw moments -------------------------------------------------------------
 
@@ -196,20 +205,26 @@ __device__ __forceinline__ void reconstruct(const RawMoments<L, C>& m, const Lat
   const C kap = recip(C(1) + s.xh * pp->invPr);
   C Sg[3][3];
   C trS = C(0);
+  // symmetric tensors: the upper entries, mirrored (the lower ones would be
+  // the same values in another rounding order)
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int j = 0; j < D; ++j)
+    for (int j = i; j < D; ++j) {
       Sg[i][j] = a2b[i][j] - s.rho * s.u[i] * s.u[j] + hs * s.rho * (pp->g[i] * s.u[j] + s.u[i] * pp->g[j]);
+      Sg[j][i] = Sg[i][j];
+    }
 #pragma unroll
   for (int i = 0; i < D; ++i) trS += Sg[i][i];
   const C b = pp->b;
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
+    for (int j = i; j < D; ++j) {
       s.sigma[i][j] = kap * (Sg[i][j] - (i == j ? trS * C(1.0 / D) : C(0)));
       s.Lam[i][j] = (i == j ? s.theta : C(0)) + b * s.sigma[i][j] * s.irho;
+      s.sigma[j][i] = s.sigma[i][j];
+      s.Lam[j][i] = s.Lam[i][j];
     }
 }
 
@@ -220,8 +235,10 @@ __device__ __forceinline__ void es3_and_a2(const CellState<L, C>& s, C (&A3)[3][
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int j = 0; j < D; ++j)
+    for (int j = i; j < D; ++j) {
       a2[i][j] = s.rho * s.u[i] * s.u[j] + (i == j ? s.rho * s.theta : C(0)) + s.sigma[i][j];
+      a2[j][i] = a2[i][j];
+    }
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -351,7 +368,7 @@ __device__ __forceinline__ void poly_coeffs(const RawMoments<L, C>& m, const Cel
   for (int i = 0; i < D; ++i) {
     C t = C(0);
 #pragma unroll
-    for (int j = 0; j < D; ++j) t += c3[i][j][j];
+    for (int j = 0; j < D; ++j) t += j < i ? c3[j][j][i] : c3[i][j][j];   // c3 is symmetric: sorted indices
     K1[i] = r * (c1[i] - C(0.5) * t);
   }
 #pragma unroll
@@ -395,9 +412,36 @@ __device__ __forceinline__ void poly_coeffs(const RawMoments<L, C>& m, const Cel
 
 }
 
+// The relaxed population (1 - omega) h + poly rounded to the storage type:
+// in the compute type one FMA, then the conversion; for FP16 storage one
+// mixed-precision FMA that rounds the FP32 operands' exact result once to
+// FP16 (v_fma_mixlo_f16), the same in every kernel.
+template <typename S, typename C>
+__device__ __forceinline__ S relax_store(C omw, C h, C poly) {
+  return narrow<S, C>(fmac(omw, h, poly));
+}
+template <>
+__device__ __forceinline__ _Float16 relax_store<_Float16, float>(float omw, float h, float poly) {
+  unsigned int d;
+  asm("v_fma_mixlo_f16 %0, %1, %2, %3 op_sel_hi:[0,0,0]" : "=v"(d) : "v"(omw), "v"(h), "v"(poly));
+  return __builtin_bit_cast(_Float16, static_cast<unsigned short>(d & 0xffffu));
+}
+
+// Collision of one cell: h holds the pre-collision populations (compute
+// type); out receives the post-collision populations in the storage type S.
+template <class L, typename C, typename S>
+__device__ __forceinline__ void collide_to(const C (&h)[L::Q], S (&out)[L::Q], const LatConsts<C>* __restrict__ lc,
+                                           const ProbParams<C>* __restrict__ pp, CellState<L, C>& s);
+
 template <class L, typename C>
 __device__ __forceinline__ void collide(C (&h)[L::Q], const LatConsts<C>* __restrict__ lc,
                                         const ProbParams<C>* __restrict__ pp, CellState<L, C>& s) {
+  collide_to<L, C, C>(h, h, lc, pp, s);
+}
+
+template <class L, typename C, typename S>
+__device__ __forceinline__ void collide_to(const C (&h)[L::Q], S (&out)[L::Q], const LatConsts<C>* __restrict__ lc,
+                                           const ProbParams<C>* __restrict__ pp, CellState<L, C>& s) {
   constexpr int D = L::D, P = L::P, N = L::N;
   const bool force = pp->force != 0;
   RawMoments<L, C> m;
@@ -407,7 +451,7 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const LatConsts<C>* __rest
   poly_coeffs<L, C>(m, s, lc, pp, K0, K1, K2, K3, K4);
   const C om = s.omega;
   const C omw = C(1) - om;
-  h[0] = fmac(omw, h[0], K0);
+  out[0] = relax_store<S, C>(omw, h[0], K0);
 #pragma unroll
   for (int p = 1; p <= P; ++p) {
     const int e[3] = {L::E[p - 1][0], L::E[p - 1][1], L::E[p - 1][2]};
@@ -435,10 +479,10 @@ __device__ __forceinline__ void collide(C (&h)[L::Q], const LatConsts<C>* __rest
             for (int l = k; l < D; ++l)
               E = addk(E, K4[i][j][k][l], mult4(i, j, k, l) * e[i] * e[j] * e[k] * e[l]);
     }
-    const C hp = fmac(omw, h[p], E + O);
-    const C hm = fmac(omw, h[p + P], E - O);
-    h[p] = hp;
-    h[p + P] = hm;
+    const S hp = relax_store<S, C>(omw, h[p], E + O);
+    const S hm = relax_store<S, C>(omw, h[p + P], E - O);
+    out[p] = hp;
+    out[p + P] = hm;
   }
 }
 

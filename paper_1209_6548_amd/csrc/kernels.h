@@ -31,6 +31,9 @@ struct StepArgs {
 // red_part).
 uint32_t slot_blocks(const Geometry& g);
 hipError_t launch_step(int velset, int storage, const StepArgs& a);
+// Step `phase` (1 or 2) of the in-place pair on the buffer a.dst (a.src is
+// not used); wall partial sums from a.wp_src to a.wp_dst as launch_step.
+hipError_t launch_pair_step(int velset, int storage, int phase, const StepArgs& a);
 hipError_t launch_reduce(int velset, int storage, const StepArgs& a);
 hipError_t launch_reduce_finalize(const double* part, uint32_t nparts, double* out, hipStream_t stream);
 hipError_t launch_moments(int velset, int storage, const StepArgs& a, uint32_t c0, uint32_t count, double* out);

@@ -99,13 +99,61 @@ k_step(Geometry geo, const S* __restrict__ src, S* __restrict__ dst, const typen
     C h[L::Q];
     gather_wave<L, S, C, C>(h, src, geo, sl.s, sl.i, p, wp_src, pp, mode);
     CellState<L, C> st;
-    collide<L, C>(h, lc, pp, st);
+    S hs[L::Q];
+    collide_to<L, C, S>(h, hs, lc, pp, st);
     const uint32_t bb = geo.sstride * uint32_t(sizeof(S)), pb = geo.pstride * uint32_t(sizeof(S));
     const Rsrc out = block_rsrc(reinterpret_cast<char*>(dst) + size_t(sl.s) * bb, bb);
 #pragma unroll
-    for (int a = 0; a < L::Q; ++a) buf_st<S>(narrow<S, C>(h[a]), out, sl.i * uint32_t(sizeof(S)), uint32_t(a) * pb);
-    if (geo.walls)
-      write_wall_partials<L, S, C>([&](int a) { return narrow<S, C>(h[a]); }, p, geo, lc, wp_dst);
+    for (int a = 0; a < L::Q; ++a) buf_st<S>(hs[a], out, sl.i * uint32_t(sizeof(S)), uint32_t(a) * pb);
+    if (geo.walls) write_wall_partials<L, S, C>([&](int a) { return hs[a]; }, p, geo, lc, wp_dst);
+    if (REDUCE) cell_contrib<L, C, C>(st, uprev, sl.s * geo.inner + sl.i, geo.ncells, have_prev, v);
+  }
+  if (REDUCE) block_reduce_write(v, red_part + size_t(blk) * NRED);
+}
+
+// One step of the in-place pair (the layout is described in stream.h): PHASE
+// 1 pulls from the buffer and pushes to the opposite planes of the forward
+// neighbours; PHASE 2 reads its own cell's opposite planes and writes its own
+// planes. The cell arithmetic (collision, wall partial sums, reductions) is
+// k_step's, so the pair gives the same bits as two steps through two
+// buffers. Only for fully diffuse (or no) walls: a specular image would need
+// the values pushed across a wall.
+template <class L, typename S, int PHASE, bool REDUCE>
+__global__ void __launch_bounds__(BLOCK)
+k_pair(Geometry geo, S* buf, const typename StepT<S>::type* __restrict__ wp_src,
+       typename StepT<S>::type* __restrict__ wp_dst, const LatConsts<typename StepT<S>::type>* __restrict__ lc,
+       const ProbParams<typename StepT<S>::type>* __restrict__ pp, typename StepT<S>::type* __restrict__ uprev,
+       int have_prev, double* __restrict__ red_part, int rev) {
+  using C = typename StepT<S>::type;
+  const uint32_t blk = tile_of(blockIdx.x, gridDim.x, rev);
+  const Slot sl = slot_of(blk, geo);
+  double v[NRED];
+  if (REDUCE) {
+#pragma unroll
+    for (int k = 0; k < NRED; ++k) v[k] = 0.0;
+  }
+  if (sl.active) {
+    const CellPos p = slice_pos<L>(sl.s, sl.i, geo);
+    C h[L::Q];
+    PullMode mode = PULL_EDGE;
+    if (PHASE == 1) {
+      mode = pull_mode_wave<L>(sl.s, p, geo);
+      gather_wave<L, S, C, C>(h, buf, geo, sl.s, sl.i, p, wp_src, pp, mode);
+    } else {
+      gather_local<L, S, C, C>(h, buf, geo, sl.s, sl.i, p, wp_src, pp);
+    }
+    CellState<L, C> st;
+    S hs[L::Q];
+    collide_to<L, C, S>(h, hs, lc, pp, st);
+    if (PHASE == 1) {
+      scatter_wave<L, S>(hs, buf, geo, sl.s, sl.i, p, mode);
+    } else {
+      const uint32_t bb = geo.sstride * uint32_t(sizeof(S)), pb = geo.pstride * uint32_t(sizeof(S));
+      const Rsrc out = block_rsrc(reinterpret_cast<char*>(buf) + size_t(sl.s) * bb, bb);
+#pragma unroll
+      for (int a = 0; a < L::Q; ++a) buf_st<S>(hs[a], out, sl.i * uint32_t(sizeof(S)), uint32_t(a) * pb);
+    }
+    if (geo.walls) write_wall_partials<L, S, C>([&](int a) { return hs[a]; }, p, geo, lc, wp_dst);
     if (REDUCE) cell_contrib<L, C, C>(st, uprev, sl.s * geo.inner + sl.i, geo.ncells, have_prev, v);
   }
   if (REDUCE) block_reduce_write(v, red_part + size_t(blk) * NRED);
@@ -353,6 +401,25 @@ static hipError_t step_t(const StepArgs& a) {
   return hipGetLastError();
 }
 
+template <class L, typename S, int PHASE>
+static hipError_t pair_t(const StepArgs& a) {
+  using C = typename StepT<S>::type;
+  const uint32_t nb = slot_blocks(a.geo);
+  S* buf = static_cast<S*>(a.dst);
+  if (a.reduce) {
+    hipLaunchKernelGGL((k_pair<L, S, PHASE, true>), dim3(nb), dim3(BLOCK), 0, a.stream, a.geo, buf,
+                       static_cast<const C*>(a.wp_src), static_cast<C*>(a.wp_dst),
+                       static_cast<const LatConsts<C>*>(a.lc), static_cast<const ProbParams<C>*>(a.pp),
+                       static_cast<C*>(a.uprev), a.have_prev, a.red_part, a.rev);
+  } else {
+    hipLaunchKernelGGL((k_pair<L, S, PHASE, false>), dim3(nb), dim3(BLOCK), 0, a.stream, a.geo, buf,
+                       static_cast<const C*>(a.wp_src), static_cast<C*>(a.wp_dst),
+                       static_cast<const LatConsts<C>*>(a.lc), static_cast<const ProbParams<C>*>(a.pp),
+                       static_cast<C*>(a.uprev), a.have_prev, a.red_part, a.rev);
+  }
+  return hipGetLastError();
+}
+
 template <class L, typename S>
 static hipError_t reduce_t(const StepArgs& a) {
   using C = typename StepT<S>::type;
@@ -411,6 +478,11 @@ static hipError_t partials_t(const StepArgs& a) {
 
 hipError_t launch_step(int velset, int storage, const StepArgs& a) {
   ESBGK_DISPATCH(velset, storage, (step_t<L, S>(a)));
+}
+
+hipError_t launch_pair_step(int velset, int storage, int phase, const StepArgs& a) {
+  if (phase == 1) ESBGK_DISPATCH(velset, storage, (pair_t<L, S, 1>(a)));
+  ESBGK_DISPATCH(velset, storage, (pair_t<L, S, 2>(a)));
 }
 
 hipError_t launch_reduce(int velset, int storage, const StepArgs& a) {

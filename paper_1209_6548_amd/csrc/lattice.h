@@ -54,6 +54,12 @@ __host__ __device__ constexpr int ecomp(int alpha, int a) {
   return alpha == 0 ? 0 : (alpha <= L::P ? L::E[alpha - 1][a] : -L::E[alpha - 1 - L::P][a]);
 }
 
+// The velocity -e_alpha.
+template <class L>
+__host__ __device__ constexpr int opposite(int alpha) {
+  return alpha == 0 ? 0 : (alpha <= L::P ? alpha + L::P : alpha - L::P);
+}
+
 // The velocity whose last component (the wall normal) is that of alpha
 // negated and whose other components are alpha's: the specular image at a
 // wall across the last axis.

@@ -258,6 +258,104 @@ __device__ __forceinline__ void gather_wave(C (&h)[L::Q], const S* __restrict__ 
   }
 }
 
+// ---- the in-place step pair ----------------------------------------------
+//
+// Two consecutive steps can share one population buffer. Step one pulls as
+// gather_wave does (the buffer holds each cell's post-collision values in
+// their own planes) and pushes its post-collision value of velocity b to the
+// plane of -e_b at the cell x + e_b: exactly the slot from which the cell
+// pulled velocity -e_b, so no other cell reads or writes it. The buffer then
+// holds, at plane -e_b of every cell y, the value that streams into y along
+// e_b. Step two reads those planes at its own cell, collides, and writes
+// every velocity to its own plane at its own cell, which restores the layout
+// of step one's input. Populations streaming in from beyond a diffuse wall
+// are the wall ghosts in both steps (no cell pushed them), and a push that
+// crosses a wall is dropped (the wall partial sums carry it).
+
+// Push the post-collision populations (storage type) of a wavefront's cells (slice s,
+// in-slice index i, position p): velocity b to the plane of -e_b at the cell
+// x + e_b. Pull modes as gather_wave's: FAST and WRAP use the window of
+// slice blocks s-3..s+3, EDGE one slice block per velocity (the periodic
+// wrap, or no store across a wall).
+template <class L, typename S>
+__device__ __forceinline__ void scatter_wave(const S (&h)[L::Q], S* buf, const Geometry& geo, uint32_t s,
+                                             uint32_t i, const CellPos& p, PullMode mode) {
+  constexpr int D = L::D, Q = L::Q;
+  constexpr uint32_t ss = sizeof(S);
+  const uint32_t bb = geo.sstride * ss;
+  const uint32_t pb = geo.pstride * ss;
+  if (mode == PULL_EDGE) {
+    int xo[7], yo[7];
+    inslice_offsets<L>(p, geo, xo, yo);          // xo[k + 3] = x - k wrapped
+    const int ns = int(geo.nslices);
+#pragma unroll
+    for (int b = 0; b < Q; ++b) {
+      const int ex = ecomp<L>(b, 0), ey = ecomp<L>(b, 1), es = ecomp<L>(b, D - 1);
+      int s2 = int(s) + es;
+      if (geo.walls && (s2 < 0 || s2 >= ns)) continue;
+      s2 = wrapc(s2, ns);
+      const uint32_t col = uint32_t(xo[3 - ex] + yo[3 - ey]);
+      const Rsrc blk = block_rsrc(reinterpret_cast<char*>(buf) + size_t(s2) * bb, bb);
+      buf_st<S>(h[b], blk, col * ss, uint32_t(opposite<L>(b)) * pb);
+    }
+    return;
+  }
+  const Rsrc win = block_rsrc(reinterpret_cast<char*>(buf) + size_t(s - 3u) * bb, 7u * bb);
+  if (mode == PULL_FAST) {
+    const uint32_t nxb = geo.nx * ss;
+    const uint32_t voff = i * ss;
+#pragma unroll
+    for (int b = 0; b < Q; ++b) {
+      const int ex = ecomp<L>(b, 0), ey = ecomp<L>(b, 1), es = ecomp<L>(b, D - 1);
+      const uint32_t soff = uint32_t(3 + es) * bb + uint32_t(opposite<L>(b)) * pb + uint32_t(int(ss) * ex) +
+                            (D == 3 ? uint32_t(ey) * nxb : 0u);
+      buf_st<S>(h[b], win, voff, soff);
+    }
+    return;
+  }
+  int xo[7], yo[7];
+  inslice_offsets<L>(p, geo, xo, yo);
+#pragma unroll
+  for (int b = 0; b < Q; ++b) {
+    const int ex = ecomp<L>(b, 0), ey = ecomp<L>(b, 1), es = ecomp<L>(b, D - 1);
+    const uint32_t off = uint32_t(xo[3 - ex] + yo[3 - ey]) * ss;
+    buf_st<S>(h[b], win, off, uint32_t(3 + es) * bb + uint32_t(opposite<L>(b)) * pb);
+  }
+}
+
+// Step two's read: velocity a of the wavefront's cells from the plane of -e_a
+// at the cell itself; within three layers of a diffuse wall, a population
+// whose source lies beyond the wall is the wall ghost.
+template <class L, typename S, typename C, typename P>
+__device__ __forceinline__ void gather_local(C (&h)[L::Q], const S* buf, const Geometry& geo, uint32_t s,
+                                             uint32_t i, const CellPos& p, const P* __restrict__ wp,
+                                             const ProbParams<C>* __restrict__ pp) {
+  constexpr int D = L::D, Q = L::Q;
+  constexpr uint32_t ss = sizeof(S);
+  const uint32_t bb = geo.sstride * ss;
+  const uint32_t pb = geo.pstride * ss;
+  const Rsrc blk = block_rsrc(reinterpret_cast<const char*>(buf) + size_t(s) * bb, bb);
+  const int ns = int(geo.nslices);
+  const bool near = geo.walls && (s < 3u || s + 3u >= geo.nslices);
+  if (near) {
+    int xo[7], yo[7];
+    inslice_offsets<L>(p, geo, xo, yo);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
+      const int s2 = int(s) - es;
+      if (s2 < 0 || s2 >= ns) {
+        h[a] = wall_ghost<L, C, P>(a, s2 < 0 ? 0 : 1, uint32_t(xo[ex + 3] + yo[ey + 3]), geo, wp, pp);
+        continue;
+      }
+      h[a] = widen<C, S>(buf_ld<S>(blk, i * ss, uint32_t(opposite<L>(a)) * pb));
+    }
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < Q; ++a) h[a] = widen<C, S>(buf_ld<S>(blk, i * ss, uint32_t(opposite<L>(a)) * pb));
+}
+
 // Pull for a lane at an arbitrary cell (no wavefront structure assumed).
 // OffT is the element-offset type: 32-bit for buffers below 4 GiB.
 template <class L, typename S, typename C, typename P, typename OffT>
