@@ -195,7 +195,8 @@ int esbgk_set_graph_steps(esbgk_ctx* ctx, int steps);
  * lattice exceed 256 MB and one buffer does not exceed 768 MB (where they
  * were measured faster on MI355X). Pairs need a periodic lattice or fully
  * diffuse walls (gamma = 1: a specular image would need the populations
- * pushed across a wall); an odd remaining step uses two buffers. */
+ * pushed across a wall). Of an odd step count, the first step uses two
+ * buffers and the rest run in pairs. */
 int esbgk_set_inplace(esbgk_ctx* ctx, int mode);
 /* 1 if esbgk_step advances this handle in pairs (mode, walls and size as
  * above), 0 if in two buffers; E_INVALID for a null handle. */

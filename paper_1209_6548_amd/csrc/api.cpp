@@ -246,12 +246,12 @@ void drop_graphs(esbgk_ctx* c) {
 // Arguments of step `phase` of an in-place pair on the buffer holding the
 // state: the wall partial sums go from the state's to the other buffer's and
 // back, so that after the pair they sit with the state as after two steps.
-StepArgs pair_args(const esbgk_ctx* c, int phase) {
-  StepArgs a = args_at(c, c->cur);
-  a.dst = c->at(c->lay.pop[c->cur]);
+StepArgs pair_args(const esbgk_ctx* c, int phase, int cur) {
+  StepArgs a = args_at(c, cur);
+  a.dst = c->at(c->lay.pop[cur]);
   a.src = a.dst;
-  a.wp_src = c->at(c->lay.wp[phase == 1 ? c->cur : 1 - c->cur]);
-  a.wp_dst = c->at(c->lay.wp[phase == 1 ? 1 - c->cur : c->cur]);
+  a.wp_src = c->at(c->lay.wp[phase == 1 ? cur : 1 - cur]);
+  a.wp_dst = c->at(c->lay.wp[phase == 1 ? 1 - cur : cur]);
   a.rev = 0;
   return a;
 }
@@ -291,8 +291,8 @@ int build_graph(esbgk_ctx* c, int parity) {
   return ESBGK_OK;
 }
 
-// Capture graph_steps / 2 in-place pairs on the buffer `cur`.
-int build_pair_graph(esbgk_ctx* c) {
+// Capture graph_steps / 2 in-place pairs on the buffer `parity`.
+int build_pair_graph(esbgk_ctx* c, int parity) {
   if (!c->cap) {
     hipError_t e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -303,7 +303,7 @@ int build_pair_graph(esbgk_ctx* c) {
   HIP_OR_FAIL(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed), "begin capture");
   hipError_t le = hipSuccess;
   for (int i = 0; i < c->graph_steps && le == hipSuccess; ++i) {
-    StepArgs a = pair_args(c, 1 + (i & 1));
+    StepArgs a = pair_args(c, 1 + (i & 1), parity);
     a.stream = c->cap;
     if (c->heating()) le = wall_tables(c, 1, c->cap);
     if (le == hipSuccess) le = launch_pair_step(c->shape.velset, c->shape.storage, 1 + (i & 1), a);
@@ -315,10 +315,10 @@ int build_pair_graph(esbgk_ctx* c) {
     return hip_fail(c, le, "capture step pair");
   }
   if (ee != hipSuccess) return hip_fail(c, ee, "end capture");
-  hipError_t ie = hipGraphInstantiate(&c->graph_pair[c->cur], g, nullptr, nullptr, 0);
+  hipError_t ie = hipGraphInstantiate(&c->graph_pair[parity], g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (ie != hipSuccess) {
-    c->graph_pair[c->cur] = nullptr;
+    c->graph_pair[parity] = nullptr;
     return hip_fail(c, ie, "instantiate graph");
   }
   return ESBGK_OK;
@@ -733,28 +733,26 @@ int esbgk_step(esbgk_ctx* c, int64_t n) {
   const uint32_t nblocks = slot_blocks(c->geo);
   const int64_t G = c->graph_steps;
   if (G > 0 && n > 0) {
-    // capture the graphs up front so that the first replay does not wait
-    // for the host
-    if (c->pairs()) {
-      if (n >= G && !c->graph_pair[c->cur]) {
-        const int rc = build_pair_graph(c);
+    // capture the graphs of both buffers up front, so that no replay waits
+    // for a capture (an odd step count moves the state to the other buffer)
+    for (int p = 0; p < 2; ++p) {
+      hipGraphExec_t have = c->pairs() ? c->graph_pair[p] : c->graph[p];
+      if (!have) {
+        const int rc = c->pairs() ? build_pair_graph(c, p) : build_graph(c, p);
         if (rc) return rc;
       }
-    } else {
-      for (int p = 0; p < 2; ++p)
-        if (!c->graph[p]) {
-          const int rc = build_graph(c, p);
-          if (rc) return rc;
-        }
     }
   }
   while (n > 0) {
     // a whole graph when no fused reduction falls inside its G steps
     const bool red_inside = c->R > 0 && ((c->steps / c->R) + 1) * c->R <= c->steps + G;
-    if (c->pairs() && n >= 2) {
+    // in-place pairs take an even count; an odd count's single two-buffer
+    // step comes first, so that the pairs run on the buffer the state ends in
+    const bool pairs = c->pairs() && n % 2 == 0;
+    if (pairs) {
       if (G > 0 && n >= G && !red_inside) {
         if (!c->graph_pair[c->cur]) {
-          const int rc = build_pair_graph(c);
+          const int rc = build_pair_graph(c, c->cur);
           if (rc) return rc;
         }
         HIP_OR_FAIL(c, hipGraphLaunch(c->graph_pair[c->cur], c->stream), "graph launch");
@@ -763,7 +761,7 @@ int esbgk_step(esbgk_ctx* c, int64_t n) {
         continue;
       }
       for (int phase = 1; phase <= 2; ++phase) {
-        StepArgs a = pair_args(c, phase);
+        StepArgs a = pair_args(c, phase, c->cur);
         const bool red = c->R > 0 && ((c->steps + 1) % c->R == 0);
         a.reduce = red ? 1 : 0;
         if (c->heating()) HIP_OR_FAIL(c, wall_tables(c, 1, c->stream), "wall tables");
@@ -780,7 +778,7 @@ int esbgk_step(esbgk_ctx* c, int64_t n) {
       n -= 2;
       continue;
     }
-    if (G > 0 && n >= G && !red_inside) {
+    if (!c->pairs() && G > 0 && n >= G && !red_inside) {
       if (!c->graph[c->cur]) {
         const int rc = build_graph(c, c->cur);
         if (rc) return rc;

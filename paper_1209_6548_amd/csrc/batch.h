@@ -8,9 +8,9 @@
 
 namespace esbgk {
 
-// Largest workgroup of the persistent kernel, chosen so that the kernel needs
-// no scratch: FP32 and FP16 storage fit 1024 threads (at most 128 VGPRs),
-// FP64 256.
+// Largest workgroup of the persistent kernel: FP32 and FP16 storage fit
+// 1024 threads (128 VGPRs; three values outside the per-cell work spill to
+// scratch), FP64 256.
 constexpr int batch_max_threads(size_t storage_bytes) {
   return storage_bytes == 8 ? 256 : 1024;
 }

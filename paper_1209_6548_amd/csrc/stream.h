@@ -211,27 +211,40 @@ __device__ __forceinline__ void gather_wave(C (&h)[L::Q], const S* __restrict__ 
   const uint32_t bb = geo.sstride * ss;         // bytes of one slice block
   const uint32_t pb = geo.pstride * ss;         // bytes of one velocity plane segment
   if (mode == PULL_EDGE) {
-    // source slice s - e_s is wave-uniform: a ghost beyond a wall, else one
-    // slice block (wrapped along a periodic slice axis)
+    // source slice s - e_s is wave-uniform: one slice block (wrapped along a
+    // periodic slice axis), or a ghost beyond a wall. Every velocity is
+    // loaded first (a source beyond a wall reads the wavefront's own slice,
+    // a value the ghost then replaces), so that all Q loads are in flight
+    // together: a load and its widening inside a branch would be waited for
+    // before the next velocity's load is issued.
     int xo[7], yo[7];
     inslice_offsets<L>(p, geo, xo, yo);
     const int ns = int(geo.nslices);
+    S raw[Q];
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
       const uint32_t col = uint32_t(xo[ex + 3] + yo[ey + 3]);
-      int s2 = int(s) - es;
-      if (geo.walls && (s2 < 0 || s2 >= ns)) {
+      const int s2 = int(s) - es;
+      const int sl = (s2 < 0 || s2 >= ns) ? (geo.walls ? int(s) : wrapc(s2, ns)) : s2;
+      const Rsrc blk = block_rsrc(reinterpret_cast<const char*>(src) + size_t(sl) * bb, bb);
+      raw[a] = buf_ld<S>(blk, col * ss, uint32_t(a) * pb);
+    }
+#pragma unroll
+    for (int a = 0; a < Q; ++a) h[a] = widen<C, S>(raw[a]);
+    if (geo.walls && (s < 3u || s + 3u >= geo.nslices)) {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
+        const int s2 = int(s) - es;
+        if (s2 >= 0 && s2 < ns) continue;
+        const uint32_t col = uint32_t(xo[ex + 3] + yo[ey + 3]);
         const int m = mirror_layer(s2, ns);
         h[a] = wall_pull<L, C, P>(a, s2 < 0 ? 0 : 1, col, geo, wp, pp, [&]() {
           const Rsrc img = block_rsrc(reinterpret_cast<const char*>(src) + size_t(m) * bb, bb);
           return widen<C, S>(buf_ld<S>(img, col * ss, uint32_t(mirror<L>(a)) * pb));
         });
-        continue;
       }
-      s2 = wrapc(s2, ns);
-      const Rsrc blk = block_rsrc(reinterpret_cast<const char*>(src) + size_t(s2) * bb, bb);
-      h[a] = widen<C, S>(buf_ld<S>(blk, col * ss, uint32_t(a) * pb));
     }
     return;
   }
@@ -335,54 +348,69 @@ __device__ __forceinline__ void gather_local(C (&h)[L::Q], const S* buf, const G
   const uint32_t bb = geo.sstride * ss;
   const uint32_t pb = geo.pstride * ss;
   const Rsrc blk = block_rsrc(reinterpret_cast<const char*>(buf) + size_t(s) * bb, bb);
-  const int ns = int(geo.nslices);
-  const bool near = geo.walls && (s < 3u || s + 3u >= geo.nslices);
-  if (near) {
+  // every plane is read (all loads in flight together), then the ghosts
+  // replace the populations whose source lies beyond a wall
+  S raw[Q];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) raw[a] = buf_ld<S>(blk, i * ss, uint32_t(opposite<L>(a)) * pb);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) h[a] = widen<C, S>(raw[a]);
+  if (geo.walls && (s < 3u || s + 3u >= geo.nslices)) {
+    const int ns = int(geo.nslices);
     int xo[7], yo[7];
     inslice_offsets<L>(p, geo, xo, yo);
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
       const int s2 = int(s) - es;
-      if (s2 < 0 || s2 >= ns) {
-        h[a] = wall_ghost<L, C, P>(a, s2 < 0 ? 0 : 1, uint32_t(xo[ex + 3] + yo[ey + 3]), geo, wp, pp);
-        continue;
-      }
-      h[a] = widen<C, S>(buf_ld<S>(blk, i * ss, uint32_t(opposite<L>(a)) * pb));
+      if (s2 >= 0 && s2 < ns) continue;
+      h[a] = wall_ghost<L, C, P>(a, s2 < 0 ? 0 : 1, uint32_t(xo[ex + 3] + yo[ey + 3]), geo, wp, pp);
     }
-    return;
   }
-#pragma unroll
-  for (int a = 0; a < Q; ++a) h[a] = widen<C, S>(buf_ld<S>(blk, i * ss, uint32_t(opposite<L>(a)) * pb));
 }
 
 // Pull for a lane at an arbitrary cell (no wavefront structure assumed).
-// OffT is the element-offset type: 32-bit for buffers below 4 GiB.
+// OffT is the element-offset type: 32-bit for buffers below 4 GiB. As in the
+// wavefront pulls, all Q loads are issued before any is used (a source
+// beyond a wall reads the lane's own slice), and the lanes within three
+// layers of a wall then replace those populations by the wall ghosts.
 template <class L, typename S, typename C, typename P, typename OffT>
 __device__ __forceinline__ void gather_lane(C (&h)[L::Q], const S* __restrict__ src, const Geometry& geo,
                                             const CellPos& p, const P* __restrict__ wp,
                                             const ProbParams<C>* __restrict__ pp) {
   constexpr int D = L::D, Q = L::Q;
-  int xo[7], yo[7];
-  inslice_offsets<L>(p, geo, xo, yo);
   const int ns = int(geo.nslices), s = slice_of<L>(p);
   const bool walls = geo.walls != 0;
+  S raw[Q];
+  {
+    int xo[7], yo[7];
+    inslice_offsets<L>(p, geo, xo, yo);
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
     const uint32_t off = uint32_t(xo[ex + 3] + yo[ey + 3]);
-    int s2 = s - es;
-    if (walls && (s2 < 0 || s2 >= ns)) {
+    const int s2 = s - es;
+    const int sl = (s2 < 0 || s2 >= ns) ? (walls ? s : wrapc(s2, ns)) : s2;
+    raw[a] = src[OffT(sl) * OffT(geo.sstride) + OffT(a) * OffT(geo.pstride) + OffT(off)];
+  }
+  }
+#pragma unroll
+  for (int a = 0; a < Q; ++a) h[a] = widen<C, S>(raw[a]);
+  if (walls && (s < 3 || s + 3 >= ns)) {
+    int xo[7], yo[7];
+    inslice_offsets<L>(p, geo, xo, yo);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
+      const int s2 = s - es;
+      if (s2 >= 0 && s2 < ns) continue;
+      const uint32_t off = uint32_t(xo[ex + 3] + yo[ey + 3]);
       const int m = mirror_layer(s2, ns);
       h[a] = wall_pull<L, C, P>(a, s2 < 0 ? 0 : 1, off, geo, wp, pp, [&]() {
         const OffT e = OffT(m) * OffT(geo.sstride) + OffT(mirror<L>(a)) * OffT(geo.pstride) + OffT(off);
         return widen<C, S>(src[e]);
       });
-      continue;
     }
-    if (!walls) s2 = wrapc(s2, ns);
-    const OffT e = OffT(s2) * OffT(geo.sstride) + OffT(a) * OffT(geo.pstride) + OffT(off);
-    h[a] = widen<C, S>(src[e]);
   }
 }
 

@@ -1,6 +1,6 @@
 """In-place step pairs (esbgk_set_inplace) against two-buffer steps, bit for
 bit, through the C ABI: 2-D and 3-D lattices, periodic and walled (moving,
-heated walls, unsteady heating), every storage, odd step counts (the last
+heated walls, unsteady heating), every storage, odd step counts (the first
 step then uses two buffers), graph replays and direct launches, fused
 reductions; pushes through the three pull modes (interior wavefronts, in-slice
 wrap, slices next to the walls or the periodic seam). Lattices with partial
