@@ -372,7 +372,10 @@ typedef struct esbgk_tvd esbgk_tvd;
 int esbgk_tvd_set_info(int velset, int* Q, int* N, double* c, double* w);
 /* esbgk_tvd_set_info of ESBGK_D2Q36GH: c[36][2], w[36]. */
 int esbgk_tvd_info(double* c, double* w);
-/* Device workspace bytes for the shape (0 if invalid). */
+/* Device workspace bytes for the shape (0 if invalid): two population
+ * buffers and, for ESBGK_D3Q216GH, each level's 20 raw moment sums per cell
+ * in the compute type (the step reads them instead of a second pass over the
+ * cell's 216 populations), plus constants and staging. */
 size_t esbgk_tvd_workspace_bytes(const esbgk_shape* shape);
 /* New handle on a caller-allocated, 256-byte-aligned workspace and a HIP
  * stream. Gas defaults: Kn = 0.1, Pr = 1, varpi = 0.5; g = 0. Errors:

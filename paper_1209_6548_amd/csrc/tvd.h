@@ -20,6 +20,8 @@ struct TVDArgs {
   const void* gc64;  // FP64 blocks for the read-out and init kernels
   const void* lc64;
   const void* pp64;
+  const void* msrc;  // D3Q216: raw moment sums of src (compute type, [MOM3][nslices * ipad])
+  void* mdst;        // D3Q216: raw moment sums of dst, written by the step and the walls
   hipStream_t stream;
 };
 
@@ -56,8 +58,16 @@ struct TVDWalls3 {
   C sw[2][216];
 };
 
+// Raw moment sums stored per cell beside each D3Q216 level (see Moments3):
+// drho, J[3], S2[6], S3[10], as [MOM3][nslices * ipad] of the compute type.
+constexpr int MOM3 = 20;
+
+// One step from a.src (moments a.msrc) into a.dst (moments a.mdst).
 hipError_t launch_tvd3_step(int storage, const TVDArgs& a);
+// Re-emission at both walls into a.dst, and the wall cells' moments into a.mdst.
 hipError_t launch_tvd3_walls(int storage, const TVDArgs& a, const void* walls);
+// The moment sums of the level pop into mom (after the level was set from outside).
+hipError_t launch_tvd3_rawmom(int storage, const TVDArgs& a, const void* pop, void* mom);
 // c[216][3]; u is [3][count]; noise [216][count].
 hipError_t launch_tvd3_init(int storage, const TVDArgs& a, const double* c, const double* rho, const double* u,
                             const double* T, const double* noise, double amp, uint32_t c0, uint32_t count);

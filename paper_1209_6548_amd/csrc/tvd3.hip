@@ -8,9 +8,15 @@
 // each step). Populations use the slice layout of Geometry (slice = z
 // plane, in-slice index y nx + x).
 //
-// A cell's 216 populations are streamed twice: once pair by pair into the
-// running moment sums, once more pair by pair (from L1/L2) to apply the
-// collision and the fluxes; nothing larger than a velocity pair is held.
+// The collision needs the moments of a cell's 216 populations before the
+// first of them is updated. Each level therefore carries its cells' raw
+// moment sums (Moments3, MOM3 values per cell): the step reads them for
+// level n, and while it writes level n + 1 pair by pair it sums the values it
+// stores into the moments of level n + 1. A level set from outside gets its
+// sums from k_tvd3_rawmom, and the walls kernel re-sums the wall cells it
+// re-emits. A cell's populations are thus read once per step (plus the
+// stencil neighbours), and the sums of every level are formed in the same
+// velocity order from the stored values, whichever kernel forms them.
 
 #include <hip/hip_runtime.h>
 
@@ -23,17 +29,52 @@ namespace esbgk {
 namespace {
 
 constexpr uint32_t BLOCK3 = 512;
-constexpr uint32_t Z3 = BLOCK3 / 64;   // slices per workgroup of the step kernel
+constexpr uint32_t Z3 = 8;               // slices per workgroup of the step kernel (one wavefront each)
+constexpr uint32_t STEP3 = 64 * Z3;      // its threads
 
 }  // namespace
 
-// Eight waves per SIMD (the most a SIMD holds) for FP32 compute: 64 VGPRs,
-// 67 more spilled to scratch. The pair loop is latency-bound, and the extra
-// waves hide more of it than the scratch reloads cost (128^3 FP32: 2.24 ms
-// against 2.63 at six waves and 3.21 at four).
+// Moment sums of one cell, slot e of the [MOM3][mstride] buffer.
+template <typename C>
+__device__ __forceinline__ void mom3_load(Moments3<C>& m, const C* __restrict__ mom, size_t mstride, size_t e) {
+  m.drho = mom[e];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) m.J[t] = mom[size_t(1 + t) * mstride + e];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) m.S2[t] = mom[size_t(4 + t) * mstride + e];
+#pragma unroll
+  for (int t = 0; t < 10; ++t) m.S3[t] = mom[size_t(10 + t) * mstride + e];
+}
+
+template <typename C>
+__device__ __forceinline__ void mom3_store(const Moments3<C>& m, C* __restrict__ mom, size_t mstride, size_t e) {
+  mom[e] = m.drho;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) mom[size_t(1 + t) * mstride + e] = m.J[t];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) mom[size_t(4 + t) * mstride + e] = m.S2[t];
+#pragma unroll
+  for (int t = 0; t < 10; ++t) mom[size_t(10 + t) * mstride + e] = m.S3[t];
+}
+
+// Waves per SIMD of the step kernel: FP32 compute holds the cell's
+// collision coefficients (36) and the running sums of the new level (20) in
+// registers, 128 VGPRs at four waves per SIMD; FP64 needs two registers a
+// value.
 template <typename S>
-__global__ void __launch_bounds__(BLOCK3, (sizeof(S) == 8 ? 1 : 8))
+constexpr int tvd3_waves() { return sizeof(S) == 8 ? 1 : 4; }
+
+// FP32 storage: a workgroup barrier (no memory fence) after every 8 pairs
+// keeps the stacked wavefronts, which read each other's populations as z
+// neighbours, within a few pairs of one another (128^3: 1.43 against 1.53 ms;
+// every 4 or 16 pairs: 1.43 / 1.46 ms). FP16 and FP64 ran slower with it.
+template <typename S>
+constexpr int tvd3_pace() { return sizeof(S) == 4 ? 4 : 0; }
+
+template <typename S>
+__global__ void __launch_bounds__(STEP3, tvd3_waves<S>())
 k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
+       const typename StepT<S>::type* __restrict__ msrc, typename StepT<S>::type* __restrict__ mdst,
        const GH3Consts<typename StepT<S>::type>* __restrict__ gc,
        const LatConsts<typename StepT<S>::type>* __restrict__ lc,
        const ProbParams<typename StepT<S>::type>* __restrict__ pp) {
@@ -50,10 +91,14 @@ k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t nchunks = geo.ipad >> 6;
   const uint32_t band = blk / nchunks, chunk = blk - band * nchunks;
-  const uint32_t s = band * Z3 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (s >= geo.nslices) return;
   const uint32_t i0 = chunk * 64u;
-  if (i0 >= geo.inner) return;                       // the slice's padding slots
+  if (i0 >= geo.inner) return;                       // the slice's padding slots (the whole workgroup)
+  // a wavefront beyond the last slice (the last band of a lattice whose
+  // slice count is not a multiple of Z3) runs the loop on the last slice
+  // and stores nothing, so that every wavefront meets every barrier
+  const uint32_t sw = band * Z3 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool live = sw < geo.nslices;
+  const uint32_t s = live ? sw : geo.nslices - 1;
   const uint32_t lane = threadIdx.x & 63u;
   // lanes past the end of the slice compute its last cell again and store
   // into their own padding slots (i0 + 64 <= ipad)
@@ -74,71 +119,131 @@ k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
     const int r = geo.walls ? min(max(int(s) + k, 0), ns - 1) : wrapc(int(s) + k, ns);
     row[k + 2] = block_rsrc(reinterpret_cast<const char*>(src) + size_t(r) * bb, bb);
   }
-  const Rsrc out = block_rsrc(reinterpret_cast<char*>(dst) + size_t(s) * bb, bb);
+  const Rsrc out = block_rsrc(reinterpret_cast<char*>(dst) + size_t(s) * bb, live ? bb : 0u);
+  const size_t mstride = size_t(geo.nslices) * geo.ipad;
 
-  // pass 1: moments
-  Moments3<C> acc;
-  moments3_zero<C>(acc);
-  const bool third = pp->force != 0;
-#pragma unroll 4
-  for (int p = 0; p < P; ++p) {
-    const C hp = widen<C, S>(buf_ld<S>(row[2], xo[2], uint32_t(p) * pb));
-    const C hm = widen<C, S>(buf_ld<S>(row[2], xo[2], uint32_t(p + P) * pb));
-    moments3_add<C>(acc, gc->w[p], gc->mono[p], hp, hm, third);
-  }
+  // the collision from the moments of the stored level (the third moments
+  // only with a body force)
   GH3Collision<C> k;
-  collision_gh3<C>(acc, lc, pp, k);
+  {
+    Moments3<C> acc;
+    mom3_load<C>(acc, msrc, mstride, size_t(s) * geo.ipad + i);
+    if (pp->force == 0) {
+#pragma unroll
+      for (int t = 0; t < 10; ++t) acc.S3[t] = C(0);
+    }
+    collision_gh3<C>(acc, lc, pp, k);
+  }
 
-  // pass 2: collision and fluxes, pair by pair, in the reverse of pass 1's
-  // order, so that it starts on the populations pass 1 read last (the pairs
-  // are independent: the order changes no result)
-#pragma unroll 1
-  for (int p = P - 1; p >= 0; --p) {
+  // collision and fluxes pair by pair; the stored values of the new level
+  // go into its moment sums in velocity order. The 20 loads of pair p + 1
+  // are issued before pair p is computed and stored (the compiler may not
+  // move loads through a buffer resource past the stores through another),
+  // so that one pair's memory latency overlaps the other's arithmetic.
+  auto load_pair = [&](int p, S (&v)[2][10]) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const uint32_t po = uint32_t(p + side * P) * pb;
+      const C sg = side == 0 ? C(1) : C(-1);
+      v[side][0] = buf_ld<S>(row[2], xo[2], po);
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const bool pos = sg * gc->nu[p][ax] > C(0);
+        if (ax == 0) {
+          v[side][1] = buf_ld<S>(row[2], xo[1], po);
+          v[side][2] = buf_ld<S>(row[2], xo[3], po);
+          v[side][3] = buf_ld<S>(row[2], pos ? xo[0] : xo[4], po);
+        } else if (ax == 1) {
+          v[side][4] = buf_ld<S>(row[2], yo[1], po);
+          v[side][5] = buf_ld<S>(row[2], yo[3], po);
+          v[side][6] = buf_ld<S>(row[2], pos ? yo[0] : yo[4], po);
+        } else {
+          v[side][7] = buf_ld<S>(row[1], xo[2], po);
+          v[side][8] = buf_ld<S>(row[3], xo[2], po);
+          v[side][9] = buf_ld<S>(pos ? row[0] : row[4], xo[2], po);
+        }
+      }
+    }
+  };
+  Moments3<C> nxt;
+  moments3_zero<C>(nxt);
+  auto do_pair = [&](int p, const S (&cur)[2][10]) {
     const uint32_t pop = uint32_t(p) * pb;
-    C hc[2];
-    hc[0] = widen<C, S>(buf_ld<S>(row[2], xo[2], pop));
-    hc[1] = widen<C, S>(buf_ld<S>(row[2], xo[2], pop + uint32_t(P) * pb));
     C hs[2];
-    collide_pair_gh3<C>(k, gc->mono[p], hc[0], hc[1], hs[0], hs[1]);
+    collide_pair_gh3<C>(k, gc->mono[p], widen<C, S>(cur[0][0]), widen<C, S>(cur[1][0]), hs[0], hs[1]);
+    C v[2];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const uint32_t po = pop + uint32_t(side * P) * pb;
       const C sg = side == 0 ? C(1) : C(-1);
-      const C f0 = hc[side];
+      const C f0 = widen<C, S>(cur[side][0]);
       C t = C(0);
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
         const C nu = sg * gc->nu[p][ax];
         const bool pos = nu > C(0);
-        C fm1, fp1, f2;
-        if (ax == 0) {
-          fm1 = widen<C, S>(buf_ld<S>(row[2], xo[1], po));
-          fp1 = widen<C, S>(buf_ld<S>(row[2], xo[3], po));
-          f2 = widen<C, S>(buf_ld<S>(row[2], pos ? xo[0] : xo[4], po));
-        } else if (ax == 1) {
-          fm1 = widen<C, S>(buf_ld<S>(row[2], yo[1], po));
-          fp1 = widen<C, S>(buf_ld<S>(row[2], yo[3], po));
-          f2 = widen<C, S>(buf_ld<S>(row[2], pos ? yo[0] : yo[4], po));
-        } else {
-          fm1 = widen<C, S>(buf_ld<S>(row[1], xo[2], po));
-          fp1 = widen<C, S>(buf_ld<S>(row[3], xo[2], po));
-          f2 = widen<C, S>(buf_ld<S>(pos ? row[0] : row[4], xo[2], po));
-        }
         C d, m;
-        tvd_terms<C>(pos, f2, fm1, f0, fp1, d, m);
+        tvd_terms<C>(pos, widen<C, S>(cur[side][3 * ax + 3]), widen<C, S>(cur[side][3 * ax + 1]), f0,
+                     widen<C, S>(cur[side][3 * ax + 2]), d, m);
         t = fmac(nu, d, t);
         t = fmac(gc->nk[p][ax], m, t);
       }
-      buf_st<S, tvd_store_policy<S>(L::Q)>(narrow<S, C>(hs[side] - t), out, so, po);
+      const S o = narrow<S, C>(hs[side] - t);
+      buf_st<S, tvd_store_policy<S>(L::Q)>(o, out, so, po);
+      v[side] = widen<C, S>(o);
     }
+    moments3_add<C>(nxt, gc->w[p], gc->mono[p], v[0], v[1], true);
+  };
+  // two register sets in turn (P is even): the loads of the next pair go
+  // out before the current pair is computed
+  static_assert(P % 2 == 0, "pairs in twos");
+  S b0[2][10], b1[2][10];
+  load_pair(0, b0);
+#pragma unroll 1
+  for (int p = 0; p < P; p += 2) {
+    load_pair(p + 1, b1);
+    do_pair(p, b0);
+    load_pair(p + 2 < P ? p + 2 : p + 1, b0);   // the last round loads pair P - 1 again
+    do_pair(p + 1, b1);
+    // every wavefront of the workgroup runs the same pairs
+    if constexpr (tvd3_pace<S>() > 0)
+      if ((p >> 1) % tvd3_pace<S>() == tvd3_pace<S>() - 1) __builtin_amdgcn_s_barrier();
   }
+  if (live) mom3_store<C>(nxt, mdst, mstride, size_t(s) * geo.ipad + i0 + lane);
+}
+
+// Moment sums of a level set from outside, one thread per slot of the
+// [MOM3][nslices * ipad] buffer (padding slots take the slice's last cell).
+template <typename S>
+__global__ void __launch_bounds__(BLOCK3)
+k_tvd3_rawmom(Geometry geo, const S* __restrict__ pop, typename StepT<S>::type* __restrict__ mom,
+              const GH3Consts<typename StepT<S>::type>* __restrict__ gc) {
+  using C = typename StepT<S>::type;
+  using L = D3Q216GH;
+  const uint32_t j = blockIdx.x * BLOCK3 + threadIdx.x;
+  const size_t mstride = size_t(geo.nslices) * geo.ipad;
+  if (j >= mstride) return;
+  const uint32_t s = fdiv(j, geo.div_ipad), slot = j - s * geo.ipad;
+  const uint32_t i = min(slot, geo.inner - 1);
+  const size_t elem = size_t(s) * geo.sstride + i;
+  Moments3<C> acc;
+  moments3_zero<C>(acc);
+#pragma unroll 4
+  for (int p = 0; p < L::P; ++p) {
+    const C hp = widen<C, S>(pop[size_t(p) * geo.pstride + elem]);
+    const C hm = widen<C, S>(pop[size_t(p + L::P) * geo.pstride + elem]);
+    moments3_add<C>(acc, gc->w[p], gc->mono[p], hp, hm, true);
+  }
+  mom3_store<C>(acc, mom, mstride, j);
 }
 
 // Re-emission at the z walls (Sec. 3.2) after a step, per in-slice column
-// i and wall side = blockIdx.y (see k_tvd_walls).
+// i and wall side = blockIdx.y (see k_tvd_walls); the wall cell's moment
+// sums are then formed again from its stored values.
 template <typename S>
 __global__ void __launch_bounds__(BLOCK3)
-k_tvd3_walls(Geometry geo, S* __restrict__ pop, const TVDWalls3<typename StepT<S>::type>* __restrict__ w) {
+k_tvd3_walls(Geometry geo, S* __restrict__ pop, const TVDWalls3<typename StepT<S>::type>* __restrict__ w,
+             typename StepT<S>::type* __restrict__ mom, const GH3Consts<typename StepT<S>::type>* __restrict__ gc) {
   using C = typename StepT<S>::type;
   using L = D3Q216GH;
   const uint32_t i = blockIdx.x * BLOCK3 + threadIdx.x;
@@ -153,12 +258,31 @@ k_tvd3_walls(Geometry geo, S* __restrict__ pop, const TVDWalls3<typename StepT<S
     const bool toward = side == 0 ? sz < 0 : sz > 0;
     if (toward) rho = fmac(w->kin[side][a], widen<C, S>(pop[size_t(a) * geo.pstride + ei]), rho);
   }
+  // velocity p + h P moves into the gas when the sign of its z component
+  // (that of the Courant number nu[p][2], negated for h = 1) points away
+  // from the wall
+  Moments3<C> acc;
+  moments3_zero<C>(acc);
+#pragma unroll 1
+  for (int p = 0; p < L::P; ++p) {
+    const bool up = gc->nu[p][2] > C(0);
+    C v[2];
 #pragma unroll
-  for (int a = 0; a < L::Q; ++a) {
-    const int sz = gh_sign<L>(a, 2);
-    const bool into_gas = side == 0 ? sz > 0 : sz < 0;
-    if (into_gas) pop[size_t(a) * geo.pstride + ew] = narrow<S, C>(rho * w->sw[side][a] - C(1));
+    for (int h = 0; h < 2; ++h) {
+      const int a = p + h * L::P;
+      const bool into_gas = (up != (h == 1)) == (side == 0);
+      S* e = pop + size_t(a) * geo.pstride + ew;
+      if (into_gas) {
+        const S o = narrow<S, C>(rho * w->sw[side][a] - C(1));
+        *e = o;
+        v[h] = widen<C, S>(o);
+      } else {
+        v[h] = widen<C, S>(*e);
+      }
+    }
+    moments3_add<C>(acc, gc->w[p], gc->mono[p], v[0], v[1], true);
   }
+  mom3_store<C>(acc, mom, size_t(geo.nslices) * geo.ipad, size_t(jw) * geo.ipad + i);
 }
 
 // h = rho S(T, u)/w (1 + amp xi) - 1 (eq. feq0 at N = 4, D = 3) for cells
@@ -232,9 +356,10 @@ template <typename S>
 static hipError_t tvd3_step_t(const TVDArgs& a) {
   using C = typename StepT<S>::type;
   const uint32_t nb = (a.geo.ipad >> 6) * ((a.geo.nslices + Z3 - 1) / Z3);
-  hipLaunchKernelGGL(k_tvd3<S>, dim3(nb), dim3(BLOCK3), 0, a.stream, a.geo, static_cast<const S*>(a.src),
-                     static_cast<S*>(a.dst), static_cast<const GH3Consts<C>*>(a.gc),
-                     static_cast<const LatConsts<C>*>(a.lc), static_cast<const ProbParams<C>*>(a.pp));
+  hipLaunchKernelGGL(k_tvd3<S>, dim3(nb), dim3(STEP3), 0, a.stream, a.geo, static_cast<const S*>(a.src),
+                     static_cast<S*>(a.dst), static_cast<const C*>(a.msrc), static_cast<C*>(a.mdst),
+                     static_cast<const GH3Consts<C>*>(a.gc), static_cast<const LatConsts<C>*>(a.lc),
+                     static_cast<const ProbParams<C>*>(a.pp));
   return hipGetLastError();
 }
 
@@ -243,7 +368,18 @@ static hipError_t tvd3_walls_t(const TVDArgs& a, const void* walls) {
   using C = typename StepT<S>::type;
   const dim3 grid((a.geo.inner + BLOCK3 - 1) / BLOCK3, 2);
   hipLaunchKernelGGL(k_tvd3_walls<S>, grid, dim3(BLOCK3), 0, a.stream, a.geo, static_cast<S*>(a.dst),
-                     static_cast<const TVDWalls3<C>*>(walls));
+                     static_cast<const TVDWalls3<C>*>(walls), static_cast<C*>(a.mdst),
+                     static_cast<const GH3Consts<C>*>(a.gc));
+  return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t tvd3_rawmom_t(const TVDArgs& a, const void* pop, void* mom) {
+  using C = typename StepT<S>::type;
+  const size_t slots = size_t(a.geo.nslices) * a.geo.ipad;
+  const uint32_t nb = uint32_t((slots + BLOCK3 - 1) / BLOCK3);
+  hipLaunchKernelGGL(k_tvd3_rawmom<S>, dim3(nb), dim3(BLOCK3), 0, a.stream, a.geo, static_cast<const S*>(pop),
+                     static_cast<C*>(mom), static_cast<const GH3Consts<C>*>(a.gc));
   return hipGetLastError();
 }
 
@@ -269,6 +405,10 @@ hipError_t launch_tvd3_step(int storage, const TVDArgs& a) { ESBGK_TVD3_DISPATCH
 
 hipError_t launch_tvd3_walls(int storage, const TVDArgs& a, const void* walls) {
   ESBGK_TVD3_DISPATCH(storage, (tvd3_walls_t<S>(a, walls)));
+}
+
+hipError_t launch_tvd3_rawmom(int storage, const TVDArgs& a, const void* pop, void* mom) {
+  ESBGK_TVD3_DISPATCH(storage, (tvd3_rawmom_t<S>(a, pop, mom)));
 }
 
 hipError_t launch_tvd3_init(int storage, const TVDArgs& a, const double* c, const double* rho, const double* u,

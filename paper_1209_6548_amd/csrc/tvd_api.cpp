@@ -63,7 +63,7 @@ size_t ssize(int storage) { return storage == ESBGK_F64 ? 8 : (storage == ESBGK_
 size_t csize(int storage) { return storage == ESBGK_F64 ? 8 : 4; }
 
 struct TLayout {
-  size_t pop[2], gc, lc, pp, gc64, lc64, pp64, walls, c, staging, total;
+  size_t pop[2], mom[2], gc, lc, pp, gc64, lc64, pp64, walls, c, staging, total;
 };
 
 bool valid_tvd_shape(const esbgk_shape* s, Geometry* g, std::string* why) {
@@ -107,6 +107,10 @@ TLayout tlayout(const esbgk_shape* s, const Geometry& g) {
   auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
   L.pop[0] = take(size_t(g.nslices) * g.sstride * ss);
   L.pop[1] = take(size_t(g.nslices) * g.sstride * ss);
+  // D3Q216: each level's raw moment sums, [MOM3][nslices * ipad] of the compute type
+  const size_t mom = d3 ? size_t(MOM3) * g.nslices * g.ipad * cs : 0;
+  L.mom[0] = take(mom);
+  L.mom[1] = take(mom);
   L.gc = take(cs == 8 ? gc64 : gc32);
   L.lc = take(cs == 8 ? sizeof(LatConsts<double>) : sizeof(LatConsts<float>));
   L.pp = take(cs == 8 ? sizeof(ProbParams<double>) : sizeof(ProbParams<float>));
@@ -200,6 +204,7 @@ struct esbgk_tvd {
   hipStream_t stream = nullptr;
   int cur = 0;
   bool state_set = false;
+  bool mom_ok = false;          // D3Q216: lay.mom[cur] holds the sums of lay.pop[cur]
   int64_t steps = 0;
   int sticky = 0;
   std::string err;
@@ -250,6 +255,8 @@ TVDArgs targs(const esbgk_tvd* c) {
   a.gc64 = c->at(c->lay.gc64);
   a.lc64 = c->at(c->lay.lc64);
   a.pp64 = c->at(c->lay.pp64);
+  a.msrc = c->set.D == 3 ? c->at(c->lay.mom[c->cur]) : nullptr;
+  a.mdst = c->set.D == 3 ? c->at(c->lay.mom[1 - c->cur]) : nullptr;
   a.stream = c->stream;
   return a;
 }
@@ -524,6 +531,7 @@ int esbgk_tvd_init_equilibrium(esbgk_tvd* c, const double* rho, const double* u,
     TVD_HIP(c, hipStreamSynchronize(c->stream), "init");
   }
   c->state_set = true;
+  c->mom_ok = false;
   c->steps = 0;
   return ESBGK_OK;
 }
@@ -547,6 +555,7 @@ int esbgk_tvd_set_populations(esbgk_tvd* c, const double* h) {
     TVD_HIP(c, hipStreamSynchronize(c->stream), "set populations");
   }
   c->state_set = true;
+  c->mom_ok = false;
   c->steps = 0;
   return ESBGK_OK;
 }
@@ -576,6 +585,10 @@ int esbgk_tvd_step(esbgk_tvd* c, int64_t n) {
   for (int64_t k = 0; k < n; ++k) {
     const TVDArgs a = targs(c);
     if (c->set.D == 3) {
+      if (!c->mom_ok) {
+        TVD_HIP(c, launch_tvd3_rawmom(c->shape.storage, a, a.src, c->at(c->lay.mom[c->cur])), "moment sums");
+        c->mom_ok = true;
+      }
       TVD_HIP(c, launch_tvd3_step(c->shape.storage, a), "step");
       if (c->shape.walls) TVD_HIP(c, launch_tvd3_walls(c->shape.storage, a, c->at(c->lay.walls)), "walls");
     } else {
