@@ -158,14 +158,15 @@ def bench_couette_persistent(cfg, steps):
     return dict(steps=steps, ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6)
 
 
-def bench_batch(r, steps, warmup, fp64_sample=16):
+def bench_batch(r, steps, warmup, fp64_sample=16, storage="f32"):
     """Batched channels in one persistent launch vs. the same channels stepped
-    one problem at a time with the FP64 single-lattice path."""
+    one problem at a time with the FP64 single-lattice path (fp64_sample
+    problems; 0 skips that comparison)."""
     import torch
 
     from paper_1209_6548_amd import Batch, make_problem, workloads
     specs = workloads.channel_batch(r)
-    probs = [make_problem("D2Q37", s["dims"][0], s["dims"][1], storage="f32", Kn=s["Kn"], Pr=s["Pr"],
+    probs = [make_problem("D2Q37", s["dims"][0], s["dims"][1], storage=storage, Kn=s["Kn"], Pr=s["Pr"],
                           T_w=s["T_w"], u_w=s["u_w"], g=s["g"]) for s in specs]
     cells = sum(s["dims"][0] * s["dims"][1] for s in specs)
     b = Batch(probs)
@@ -188,6 +189,8 @@ def bench_batch(r, steps, warmup, fp64_sample=16):
                ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6,
                finite=bool(all(np.isfinite(x["mass"]) and np.isfinite(x["energy"]) for x in red)))
     b.close()
+    if fp64_sample == 0:
+        return out
     # per-problem FP64 loop on a sample of the same problems (same per-step work)
     rng = np.random.default_rng(0)
     pick = rng.choice(len(specs), fp64_sample, replace=False)
@@ -386,6 +389,10 @@ def main():
         variants["batched_channels"]["regime"] = ("cache-resident (about 160 MB of populations, inside the "
                                                   "256 MB Infinity Cache): not an HBM-roofline regime")
         log(f"batch: {variants['batched_channels']['mlups']:.0f} MLUPS")
+        variants["batched_channels_f16"] = bench_batch(r, max(1000, 5 * args.steps), max(100, args.warmup),
+                                                       fp64_sample=0, storage="f16")
+        variants["batched_channels_f16"]["regime"] = "cache-resident (about 80 MB of populations)"
+        log(f"batch f16: {variants['batched_channels_f16']['mlups']:.0f} MLUPS")
         r3 = lattice_info("D3Q39")["r"]
         # 3-D workloads (timed from the rest state: the step's work does not depend on it)
         box = dict(name="shear_wave_256^3", velset="D3Q39", dims=(256, 256, 256), walls=False, Kn=0.02,
