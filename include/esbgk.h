@@ -192,7 +192,7 @@ int esbgk_set_graph_steps(esbgk_ctx* ctx, int steps);
  * the bits are the same; a run of pairs works on half the memory, which
  * can then stay in the GPU's 256 MB memory-side cache. mode = 1: pairs;
  * 0: always two buffers; 2 (default): pairs when the two buffers of one
- * lattice exceed 256 MB and one buffer does not exceed 768 MB (where they
+ * lattice exceed 256 MB and one buffer does not exceed 384 MB (where they
  * were measured faster on MI355X). Pairs need a periodic lattice or fully
  * diffuse walls (gamma = 1: a specular image would need the populations
  * pushed across a wall). Of an odd step count, the first step uses two

@@ -149,13 +149,15 @@ struct esbgk_ctx {
   bool pairs() const {
     if (shape.walls && !(gam[0] == 1.0 && gam[1] == 1.0)) return false;
     if (inplace != 2) return inplace == 1;
-    // Measured on MI355X: pairs are faster when the two buffers overflow the
-    // 256 MB memory-side cache and one buffer does not exceed it by much
-    // (1024^2 D2Q37: FP32 49 against 59 us per step, FP64 108 against 113);
-    // they are 1-7 % slower when both buffers fit (FP16 at 1024^2) or when
-    // one buffer is far larger (the 3-D lattices of several GB).
+    // Measured on MI355X (D2Q37 channels, n x n): pairs are faster when the
+    // two buffers overflow the 256 MB memory-side cache and one buffer does
+    // not exceed it by much (FP32 1024^2: 47.1 against 56.1 us per step,
+    // 1448^2: 111.8 against 121.5; FP64 1024^2: 104.1 against 108.9; FP16
+    // 1448^2: 55.6 against 63.6); they are slower when both buffers fit
+    // (FP32 896^2: 37.3 against 35.1) or one buffer is twice the cache
+    // (FP32 2048^2: 236 against 219).
     const double one = double(lay.pop[1] - lay.pop[0]);
-    return 2.0 * one > MALL_BYTES && one <= 3.0 * MALL_BYTES;
+    return 2.0 * one > MALL_BYTES && one <= 1.5 * MALL_BYTES;
   }
 
   char* at(size_t off) const { return ws + off; }

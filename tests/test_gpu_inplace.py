@@ -97,3 +97,22 @@ def test_pairs_at_full_size(storage):
         lat.set_graph_steps(4)
         lat.step(6)
     np.testing.assert_array_equal(a.get_state(), b.get_state())
+
+
+@pytest.mark.parametrize("storage,n,pairs", [("f32", 896, False), ("f32", 1024, True), ("f32", 1448, True),
+                                             ("f32", 2048, False), ("f16", 1024, False), ("f16", 1448, True),
+                                             ("f64", 1024, True)])
+def test_default_mode_picks_pairs_by_size(storage, n, pairs):
+    """Mode 2 uses pairs when the two buffers overflow the 256 MB
+    memory-side cache and one buffer is at most 384 MB (the sizes where
+    pairs were measured faster)."""
+    from paper_1209_6548_amd import lattice_info, workloads
+    import bench
+    cfg = dict(workloads.poiseuille_thermal_1024(lattice_info("D2Q37")["r"]), dims=(n, n))
+    lat = bench.make_lattice(cfg, storage)
+    assert lat.inplace_active == pairs
+    lat.set_inplace(1)
+    assert lat.inplace_active
+    lat.set_inplace(0)
+    assert not lat.inplace_active
+    lat.close()
