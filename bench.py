@@ -158,19 +158,24 @@ def bench_couette_persistent(cfg, steps):
     return dict(steps=steps, ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6)
 
 
-def bench_batch(r, steps, warmup, fp64_sample=16, storage="f32"):
+def bench_batch(r, steps, warmup, fp64_sample=16, storage="f32", whole=False, **mix):
     """Batched channels in one persistent launch vs. the same channels stepped
     one problem at a time with the FP64 single-lattice path (fp64_sample
-    problems; 0 skips that comparison)."""
+    problems; 0 skips that comparison). mix: arguments of
+    workloads.channel_batch (default: the 512-channel mix); whole: keep every
+    problem in one workgroup (no cut problems) whatever the autotuner would
+    pick."""
     import torch
 
     from paper_1209_6548_amd import Batch, make_problem, workloads
-    specs = workloads.channel_batch(r)
+    specs = workloads.channel_batch(r, **mix)
     probs = [make_problem("D2Q37", s["dims"][0], s["dims"][1], storage=storage, Kn=s["Kn"], Pr=s["Pr"],
                           T_w=s["T_w"], u_w=s["u_w"], g=s["g"]) for s in specs]
     cells = sum(s["dims"][0] * s["dims"][1] for s in specs)
     b = Batch(probs)
     b.autotune(20)
+    if whole and b.split[1]:
+        b.set_split(0)
     info = b.layout_info()
     b.init_equilibrium()
     b.set_reduce_interval(1000)      # the FP64 per-problem reductions ride along every 1000 steps
@@ -184,8 +189,11 @@ def bench_batch(r, steps, warmup, fp64_sample=16, storage="f32"):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     red = b.last_reduction() if steps + warmup >= 1000 else b.reduce()
-    out = dict(problems=len(specs), cells=cells, layout=info, launch="one persistent kernel per step() call, "
-               "captured in a HIP graph and replayed", reductions="FP64 per problem, fused every 1000 steps",
+    launch = ("one launch per step (problems cut into pieces over all workgroups), replayed from graphs of "
+              "32 steps" if info["split"] else "one persistent kernel per step() call, captured in a HIP graph and "
+              "replayed")
+    out = dict(problems=len(specs), cells=cells, layout=info, launch=launch, reductions="FP64 per problem, fused "
+               "every 1000 steps",
                ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6,
                finite=bool(all(np.isfinite(x["mass"]) and np.isfinite(x["energy"]) for x in red)))
     b.close()
@@ -393,6 +401,14 @@ def main():
                                                        fp64_sample=0, storage="f16")
         variants["batched_channels_f16"]["regime"] = "cache-resident (about 80 MB of populations)"
         log(f"batch f16: {variants['batched_channels_f16']['mlups']:.0f} MLUPS")
+        # few large channels: 32 of 64 x 256..512 cells (about 24 000 each), fewer problems than compute units
+        big = dict(n=32, nx=64, ny_range=(256, 512))
+        steps_big = max(200, args.steps)
+        variants["batched_channels_32_large"] = bench_batch(r, steps_big, 20, fp64_sample=0, **big)
+        variants["batched_channels_32_large"]["whole_problems"] = bench_batch(r, steps_big, 20, fp64_sample=0,
+                                                                              whole=True, **big)
+        log(f"batch of 32 large channels: {variants['batched_channels_32_large']['mlups']:.0f} MLUPS "
+            f"(whole problems: {variants['batched_channels_32_large']['whole_problems']['mlups']:.0f})")
         r3 = lattice_info("D3Q39")["r"]
         # 3-D workloads (timed from the rest state: the step's work does not depend on it)
         box = dict(name="shear_wave_256^3", velset="D3Q39", dims=(256, 256, 256), walls=False, Kn=0.02,

@@ -290,8 +290,8 @@ int esbgk_batch_use_graphs(esbgk_batch* b, int on);
  * kernel's steps from levels R-1, 2R-1, ... (0 disables): the step's
  * reconstructed state, per-cell terms in FP64, summed per 64-cell chunk by a
  * wavefront butterfly and then over the problem's chunks in order by one
- * thread of the workgroup that owns the problem (deterministic; no
- * atomics). esbgk_batch_reduce forms them now from the stored state in FP64
+ * thread of the workgroup that owns the problem, or of a kernel after the
+ * step when problems are cut (deterministic; no atomics). esbgk_batch_reduce forms them now from the stored state in FP64
  * arithmetic and synchronises; esbgk_batch_last_reduction returns the latest
  * of either kind and synchronises (E_STATE if none has run since the state
  * was set). E_NONFINITE (sticky) if a cell of some problem has a non-finite
@@ -314,10 +314,25 @@ int esbgk_batch_layout(const esbgk_batch* b, int* threads, int* nbins);
  * rounded up to 64 cells, over the workgroup size). Either output may be
  * NULL. */
 int esbgk_batch_layout_info(const esbgk_batch* b, int* max_problems_per_bin, int64_t* max_cells_per_thread);
+/* Cut problems larger than piece_cells (a positive multiple of 64; 0 keeps
+ * every problem whole, the default) into pieces of that many cells, packed
+ * into the bins like problems, so that a batch of few large problems
+ * occupies every compute unit. A cut problem's pieces may lie in different
+ * workgroups, so each step is then its own launch (followed, on reduction
+ * steps, by a kernel that adds every problem's chunk sums in chunk order:
+ * the same bits as whole problems), replayed from graphs of up to 32 steps.
+ * Rebuilds the bins with the current workgroup size and bin count.
+ * E_INVALID for another piece_cells. esbgk_batch_split reports the piece
+ * size and whether some problem is cut (active = 1). */
+int esbgk_batch_set_split(esbgk_batch* b, int piece_cells);
+int esbgk_batch_split(const esbgk_batch* b, int* piece_cells, int* active);
 /* Autotuner: time steps_per_trial steps of every candidate layout
  * (workgroups of 256..max threads x 1, 2, 4, 8 bins per compute unit or one
- * problem per workgroup) on the uniform rest state and keep the fastest.
- * Overwrites the state: call esbgk_batch_init_equilibrium afterwards. */
+ * problem per workgroup; whole problems and, when the largest problem holds
+ * more than twice a quarter compute unit's share of the cells, pieces of
+ * that share and of a quarter of it) on the uniform rest state and keep the
+ * fastest. Overwrites the state: call esbgk_batch_init_equilibrium
+ * afterwards. */
 int esbgk_batch_autotune(esbgk_batch* b, int steps_per_trial);
 int64_t esbgk_batch_steps_done(const esbgk_batch* b);
 const char* esbgk_batch_last_error(const esbgk_batch* b);

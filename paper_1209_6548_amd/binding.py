@@ -105,6 +105,8 @@ def lib():
             "esbgk_batch_reduce": (I, [P, DP]),
             "esbgk_batch_last_reduction": (I, [P, DP]),
             "esbgk_batch_layout_info": (I, [P, P, P]),
+            "esbgk_batch_set_split": (I, [P, I]),
+            "esbgk_batch_split": (I, [P, P, P]),
             "esbgk_batch_last_error": (ctypes.c_char_p, [P]),
             "esbgk_tvd_info": (I, [DP, DP]),
             "esbgk_tvd_set_info": (I, [I, P, P, DP, DP]),
@@ -415,7 +417,21 @@ class Batch:
         mp, mc = ctypes.c_int(), ctypes.c_int64()
         self._check(lib().esbgk_batch_layout_info(self._b, ctypes.byref(mp), ctypes.byref(mc)), "batch_layout_info")
         t, nb = self.layout()
-        return dict(threads=t, bins=nb, max_problems_per_workgroup=mp.value, max_cells_per_thread=mc.value)
+        piece, active = self.split
+        return dict(threads=t, bins=nb, max_pieces_per_workgroup=mp.value, max_cells_per_thread=mc.value,
+                    piece_cells=piece, split=active)
+
+    def set_split(self, piece_cells):
+        """Cut problems larger than piece_cells (a multiple of 64; 0: whole
+        problems) into pieces spread over the workgroups."""
+        self._check(lib().esbgk_batch_set_split(self._b, int(piece_cells)), "batch_set_split")
+
+    @property
+    def split(self):
+        """(piece_cells, whether some problem is cut)."""
+        pc, act = ctypes.c_int(), ctypes.c_int()
+        self._check(lib().esbgk_batch_split(self._b, ctypes.byref(pc), ctypes.byref(act)), "batch_split")
+        return pc.value, bool(act.value)
 
     def set_reduce_interval(self, R):
         self._check(lib().esbgk_batch_set_reduce_interval(self._b, int(R)), "batch_set_reduce_interval")

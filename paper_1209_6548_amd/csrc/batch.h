@@ -43,11 +43,21 @@ struct BatchRed {
   int64_t* red_level;
 };
 
+// A bin holds pieces: piece j of the bin table is problem order[j], cells
+// [piece_c0[j], piece_c0[j] + piece_n[j]) (piece_c0 a multiple of 64). With
+// whole problems (split = 0) every piece is a whole problem and one launch
+// advances nsteps steps; with split problems (split = 1) a problem's pieces
+// may lie in several bins, so a launch advances one step and the
+// per-problem sums of a reduction are added by k_batch_sum afterwards.
 struct BatchLaunch {
   const BatchProblem* probs;
   const void* pps;            // ProbParams<C>[n]
   const uint32_t* bin_first;  // [nbins + 1] into order
-  const uint32_t* order;      // problem ids grouped by bin
+  const uint32_t* order;      // problem id of each piece, grouped by bin
+  const uint32_t* piece_c0;   // first cell of each piece
+  const uint32_t* piece_n;    // cells of each piece
+  int split;
+  uint32_t nprob;
   void* bufA;                 // the state of an even level is in A, of an odd level in B
   void* bufB;
   void* wpA;
@@ -59,8 +69,9 @@ struct BatchLaunch {
   hipStream_t stream;
 };
 
-// The persistent step kernel (nsteps steps from level *red.level), then the
-// level advanced by nsteps.
+// The persistent step kernel (nsteps steps from level *red.level; one with
+// split problems), the per-problem reduction sums when split, then the level
+// advanced by nsteps.
 hipError_t launch_batch(int velset, int storage, const BatchLaunch& a);
 // FP64 reductions of every problem at the current level (*red.level) from the
 // stored state (no step), recorded as at level `level`; pps/lc are the FP64

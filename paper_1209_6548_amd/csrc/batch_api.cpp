@@ -29,9 +29,9 @@ size_t ssize(int storage) { return storage == ESBGK_F64 ? 8 : (storage == ESBGK_
 size_t csize(int storage) { return storage == ESBGK_F64 ? 8 : 4; }
 
 struct BLayout {
-  size_t bufA, bufB, wpA, wpB, probs, pps, lc, pps64, lc64, bin_first, order, staging, total;
+  size_t bufA, bufB, wpA, wpB, probs, pps, lc, pps64, lc64, bin_first, order, piece_c0, piece_n, staging, total;
   size_t uprev, chunks, red_out, red_level, level;
-  size_t pop_elems, wp_elems;
+  size_t pop_elems, wp_elems, max_pieces;
 };
 
 constexpr const char* UNSTABLE_MSG = "Euler step unstable: dt/tau or dt/(Pr tau) >= 2";
@@ -100,8 +100,12 @@ BLayout blayout(const esbgk_problem* p, int n) {
   // FP64 blocks for the read-out kernels (the same blocks when storage is FP64)
   L.pps64 = csize(storage) == 8 ? L.pps : take(size_t(n) * sizeof(ProbParams<double>));
   L.lc64 = csize(storage) == 8 ? L.lc : take(sizeof(LatConsts<double>));
-  L.bin_first = take(size_t(n + 1) * 4);
-  L.order = take(size_t(n) * 4);
+  // pieces (whole problems, or problems cut into 64-cell chunks): at most one per chunk
+  L.max_pieces = chunks;
+  L.bin_first = take(size_t(chunks + 1) * 4);
+  L.order = take(chunks * 4);
+  L.piece_c0 = take(chunks * 4);
+  L.piece_n = take(chunks * 4);
   L.uprev = take(size_t(lat->D) * cells * csize(storage));
   L.chunks = take(chunks * NRED * sizeof(double));
   L.red_out = take(size_t(n) * NRED * sizeof(double));
@@ -127,6 +131,8 @@ struct esbgk_batch {
   bool state_set = false;
   int64_t steps = 0;
   uint32_t threads = 0, nbins = 0;
+  uint32_t piece = 0;          // cells per piece of a cut problem (a multiple of 64); 0: whole problems
+  bool split = false;          // some problem is cut into several pieces (one step per launch)
   int cus = 0;
   int sticky = 0;
   std::string err;
@@ -155,42 +161,57 @@ int bfail(esbgk_batch* b, hipError_t e, const char* where) {
     if (_e != hipSuccess) return bfail(b, _e, where);     \
   } while (0)
 
-// Longest problem first, each into the bin with the fewest cells (counted as
-// the kernel's slots: each problem rounded up to a multiple of 64).
+// The problems as pieces (b->piece cells each, whole 64-cell chunks, the
+// last piece of a problem taking the rest; whole problems when b->piece is 0
+// or not smaller), longest piece first, each into the bin with the fewest
+// slots (a piece's cells rounded up to a multiple of 64).
 int build_bins(esbgk_batch* b, uint32_t nbins) {
-  const int n = int(b->p.size());
-  nbins = std::max<uint32_t>(1, std::min<uint32_t>(nbins, uint32_t(n)));
-  std::vector<int> idx(n);
-  std::iota(idx.begin(), idx.end(), 0);
-  std::stable_sort(idx.begin(), idx.end(),
-                   [&](int x, int y) { return b->bp[x].geo.ncells > b->bp[y].geo.ncells; });
-  using Item = std::pair<uint64_t, uint32_t>;   // (cells, bin)
+  struct Piece {
+    uint32_t id, c0, n;
+  };
+  std::vector<Piece> pcs;
+  bool split = false;
+  for (size_t i = 0; i < b->p.size(); ++i) {
+    const uint32_t nc = b->bp[i].geo.ncells;
+    const uint32_t len = b->piece > 0 && b->piece < nc ? b->piece : nc;
+    split = split || len < nc;
+    for (uint32_t c0 = 0; c0 < nc; c0 += len) pcs.push_back({uint32_t(i), c0, std::min(len, nc - c0)});
+  }
+  if (pcs.size() > b->lay.max_pieces) return ESBGK_E_INVALID;   // not reached: a piece holds >= 64 cells
+  const uint32_t npc = uint32_t(pcs.size());
+  nbins = std::max<uint32_t>(1, std::min<uint32_t>(nbins, npc));
+  std::vector<uint32_t> idx(npc);
+  std::iota(idx.begin(), idx.end(), 0u);
+  std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return pcs[x].n > pcs[y].n; });
+  using Item = std::pair<uint64_t, uint32_t>;   // (slots, bin)
   std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
   for (uint32_t k = 0; k < nbins; ++k) heap.push({0, k});
   std::vector<std::vector<uint32_t>> bins(nbins);
-  std::vector<Item> full;
-  for (int i : idx) {
+  for (uint32_t j : idx) {
     Item it = heap.top();
     heap.pop();
-    while (bins[it.second].size() >= size_t(BATCH_MAX_PER_BIN)) {
-      full.push_back(it);
+    while (bins[it.second].size() >= size_t(BATCH_MAX_PER_BIN)) {   // a full bin leaves the heap
       if (heap.empty()) return ESBGK_E_INVALID;
       it = heap.top();
       heap.pop();
     }
-    bins[it.second].push_back(uint32_t(i));
-    it.first += (b->bp[i].geo.ncells + 63u) & ~63u;
+    bins[it.second].push_back(j);
+    it.first += (pcs[j].n + 63u) & ~63u;
     heap.push(it);
   }
-  std::vector<uint32_t> first(nbins + 1), order;
-  order.reserve(n);
+  std::vector<uint32_t> first(nbins + 1), order, c0s, ns;
+  order.reserve(npc);
+  c0s.reserve(npc);
+  ns.reserve(npc);
   b->bin_slots.assign(nbins, 0);
   b->bin_count.assign(nbins, 0);
   for (uint32_t k = 0; k < nbins; ++k) {
     first[k] = uint32_t(order.size());
-    for (uint32_t id : bins[k]) {
-      order.push_back(id);
-      b->bin_slots[k] += (b->bp[id].geo.ncells + 63u) & ~63u;
+    for (uint32_t j : bins[k]) {
+      order.push_back(pcs[j].id);
+      c0s.push_back(pcs[j].c0);
+      ns.push_back(pcs[j].n);
+      b->bin_slots[k] += (pcs[j].n + 63u) & ~63u;
     }
     b->bin_count[k] = uint32_t(bins[k].size());
   }
@@ -199,8 +220,12 @@ int build_bins(esbgk_batch* b, uint32_t nbins) {
        "bins");
   BHIP(b, hipMemcpyAsync(b->at(b->lay.order), order.data(), order.size() * 4, hipMemcpyHostToDevice, b->stream),
        "bins");
+  BHIP(b, hipMemcpyAsync(b->at(b->lay.piece_c0), c0s.data(), c0s.size() * 4, hipMemcpyHostToDevice, b->stream),
+       "bins");
+  BHIP(b, hipMemcpyAsync(b->at(b->lay.piece_n), ns.data(), ns.size() * 4, hipMemcpyHostToDevice, b->stream), "bins");
   BHIP(b, hipStreamSynchronize(b->stream), "bins");
   b->nbins = nbins;
+  b->split = split;
   return ESBGK_OK;
 }
 
@@ -210,6 +235,10 @@ BatchLaunch launch_args(const esbgk_batch* b, int64_t n) {
   a.pps = b->at(b->lay.pps);
   a.bin_first = reinterpret_cast<const uint32_t*>(b->at(b->lay.bin_first));
   a.order = reinterpret_cast<const uint32_t*>(b->at(b->lay.order));
+  a.piece_c0 = reinterpret_cast<const uint32_t*>(b->at(b->lay.piece_c0));
+  a.piece_n = reinterpret_cast<const uint32_t*>(b->at(b->lay.piece_n));
+  a.split = b->split ? 1 : 0;
+  a.nprob = uint32_t(b->p.size());
   a.bufA = b->at(b->lay.bufA);
   a.bufB = b->at(b->lay.bufB);
   a.wpA = b->at(b->lay.wpA);
@@ -295,6 +324,23 @@ void drop_batch_graphs(esbgk_batch* b) {
   b->graphs.clear();
 }
 
+// n steps: one persistent launch, or with split problems n launches of one
+// step each (the kernel, the per-problem sums, the level update).
+hipError_t launch_steps(const esbgk_batch* b, hipStream_t stream, int64_t n) {
+  BatchLaunch a = launch_args(b, b->split ? 1 : n);
+  a.stream = stream;
+  const int64_t launches = b->split ? n : 1;
+  for (int64_t k = 0; k < launches; ++k) {
+    const hipError_t e = launch_batch(b->velset, b->storage, a);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Largest step count captured in one graph with split problems (three
+// nodes a step).
+constexpr int64_t SPLIT_GRAPH_STEPS = 32;
+
 // The captured launch of n steps (kernel + level update), built on first use.
 int batch_graph(esbgk_batch* b, int64_t n, hipGraphExec_t* out) {
   for (auto& g : b->graphs)
@@ -311,9 +357,7 @@ int batch_graph(esbgk_batch* b, int64_t n, hipGraphExec_t* out) {
   }
   if (b->graphs.size() >= 4) drop_batch_graphs(b);   // a few step counts in use at a time
   BHIP(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "begin capture");
-  BatchLaunch a = launch_args(b, n);
-  a.stream = b->cap;
-  const hipError_t le = launch_batch(b->velset, b->storage, a);
+  const hipError_t le = launch_steps(b, b->cap, n);
   hipGraph_t g = nullptr;
   const hipError_t ee = hipStreamEndCapture(b->cap, &g);
   if (le != hipSuccess) {
@@ -494,6 +538,28 @@ int esbgk_batch_set_layout(esbgk_batch* b, int threads, int nbins) {
   return build_bins(b, uint32_t(nbins));
 }
 
+int esbgk_batch_set_split(esbgk_batch* b, int piece_cells) {
+  if (!b) return ESBGK_E_INVALID;
+  if (b->sticky) return b->sticky;
+  if (piece_cells < 0 || piece_cells % 64) {
+    b->err = "piece_cells must be 0 (whole problems) or a positive multiple of 64";
+    return ESBGK_E_INVALID;
+  }
+  drop_batch_graphs(b);
+  const uint32_t old = b->piece;
+  b->piece = uint32_t(piece_cells);
+  const int rc = build_bins(b, b->nbins);
+  if (rc) b->piece = old;
+  return rc;
+}
+
+int esbgk_batch_split(const esbgk_batch* b, int* piece_cells, int* active) {
+  if (!b) return ESBGK_E_INVALID;
+  if (piece_cells) *piece_cells = int(b->piece);
+  if (active) *active = b->split ? 1 : 0;
+  return ESBGK_OK;
+}
+
 int esbgk_batch_layout(const esbgk_batch* b, int* threads, int* nbins) {
   if (!b) return ESBGK_E_INVALID;
   if (threads) *threads = int(b->threads);
@@ -523,34 +589,54 @@ int esbgk_batch_autotune(esbgk_batch* b, int steps_per_trial) {
   std::vector<uint32_t> bins_c;
   for (int per : {1, 2, 4, 8}) bins_c.push_back(uint32_t(b->cus) * uint32_t(per));
   bins_c.push_back(uint32_t(b->p.size()));
+  // candidate pieces: whole problems, and (when the largest problem would
+  // fill a compute unit's share of the batch several times over) problems
+  // cut so that the pieces outnumber the compute units about 4 to 1
+  std::vector<uint32_t> piece_c = {0};
+  uint64_t total = 0;
+  uint32_t largest = 0;
+  for (const auto& q : b->bp) {
+    total += q.geo.ncells;
+    largest = std::max(largest, q.geo.ncells);
+  }
+  const uint64_t share = std::max<uint64_t>(64, (total / (4u * uint64_t(b->cus)) + 63) / 64 * 64);
+  if (largest > 2 * share) {
+    piece_c.push_back(uint32_t(share));
+    const uint32_t quarter = uint32_t(std::max<uint64_t>(64, share / 4 / 64 * 64));
+    if (quarter != share) piece_c.push_back(quarter);
+  }
   hipEvent_t e0, e1;
   BHIP(b, hipEventCreate(&e0), "autotune");
   BHIP(b, hipEventCreate(&e1), "autotune");
   float best = 1e30f;
-  uint32_t best_t = b->threads, best_n = b->nbins;
-  for (int t = 256; t <= maxt; t *= 2) {
-    for (uint32_t nb : bins_c) {
-      b->threads = uint32_t(t);
-      if (build_bins(b, nb) != ESBGK_OK) continue;
-      BatchLaunch a = launch_args(b, 2);
-      BHIP(b, launch_batch(b->velset, b->storage, a), "autotune");
-      a.nsteps = steps_per_trial;
-      BHIP(b, hipEventRecord(e0, b->stream), "autotune");
-      BHIP(b, launch_batch(b->velset, b->storage, a), "autotune");
-      BHIP(b, hipEventRecord(e1, b->stream), "autotune");
-      BHIP(b, hipEventSynchronize(e1), "autotune");
-      float ms = 0;
-      BHIP(b, hipEventElapsedTime(&ms, e0, e1), "autotune");
-      if (ms < best) {
-        best = ms;
-        best_t = uint32_t(t);
-        best_n = b->nbins;
+  uint32_t best_t = b->threads, best_n = b->nbins, best_p = 0;
+  for (uint32_t pc : piece_c) {
+    b->piece = pc;
+    for (int t = 256; t <= maxt; t *= 2) {
+      for (uint32_t nb : bins_c) {
+        b->threads = uint32_t(t);
+        if (build_bins(b, nb) != ESBGK_OK) continue;
+        if (pc > 0 && !b->split) continue;   // no problem was cut: the same as whole problems
+        BHIP(b, launch_steps(b, b->stream, 2), "autotune");
+        BHIP(b, hipEventRecord(e0, b->stream), "autotune");
+        BHIP(b, launch_steps(b, b->stream, steps_per_trial), "autotune");
+        BHIP(b, hipEventRecord(e1, b->stream), "autotune");
+        BHIP(b, hipEventSynchronize(e1), "autotune");
+        float ms = 0;
+        BHIP(b, hipEventElapsedTime(&ms, e0, e1), "autotune");
+        if (ms < best) {
+          best = ms;
+          best_t = uint32_t(t);
+          best_n = b->nbins;
+          best_p = pc;
+        }
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->threads = best_t;
+  b->piece = best_p;
   rc = build_bins(b, best_n);
   if (rc) return rc;
   return reset_levels(b);
@@ -578,13 +664,17 @@ int esbgk_batch_step(esbgk_batch* b, int64_t n) {
   }
   if (n == 0) return ESBGK_OK;
   if (b->use_graphs) {
-    hipGraphExec_t g = nullptr;
-    const int rc = batch_graph(b, n, &g);
-    if (rc) return rc;
-    BHIP(b, hipGraphLaunch(g, b->stream), "batch graph launch");
+    // split problems: graphs of at most SPLIT_GRAPH_STEPS steps, replayed
+    for (int64_t left = n; left > 0;) {
+      const int64_t g_n = b->split ? std::min(left, SPLIT_GRAPH_STEPS) : left;
+      hipGraphExec_t g = nullptr;
+      const int rc = batch_graph(b, g_n, &g);
+      if (rc) return rc;
+      BHIP(b, hipGraphLaunch(g, b->stream), "batch graph launch");
+      left -= g_n;
+    }
   } else {
-    BatchLaunch a = launch_args(b, n);
-    BHIP(b, launch_batch(b->velset, b->storage, a), "batch step");
+    BHIP(b, launch_steps(b, b->stream, n), "batch step");
   }
   b->parity ^= int(n & 1);
   b->steps += n;

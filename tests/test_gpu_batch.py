@@ -12,7 +12,9 @@
   with walls across z);
 * the captured-graph launch against direct launches (bit for bit), a change
   of the reduction interval between launches, and the autotuned layout's
-  report.
+  report;
+* problems cut into pieces over several workgroups (one launch per step)
+  against whole problems, bit for bit.
 """
 
 import numpy as np
@@ -213,7 +215,7 @@ def test_batch_autotune_reports_layout():
     t, nb = b.autotune(steps_per_trial=5)
     info = b.layout_info()
     assert info["threads"] == t and info["bins"] == nb
-    assert 1 <= info["max_problems_per_workgroup"] <= 48
+    assert 1 <= info["max_pieces_per_workgroup"] <= 64
     assert info["max_cells_per_thread"] >= 1
     # the state must be set again after tuning; then it steps like a fresh batch
     b.init_equilibrium()
@@ -223,3 +225,48 @@ def test_batch_autotune_reports_layout():
     ref.step(4)
     for i in (0, 17, 47):
         np.testing.assert_array_equal(b.get_populations(i), ref.get_populations(i))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batch_split_problems_equal_whole(storage, dim):
+    """Problems cut into 64- and 128-cell pieces spread over the workgroups
+    (each step its own launch, the per-problem sums added by a kernel after
+    the step) give the same populations and reductions, bit for bit, as whole
+    problems: through graphs and direct launches, with fused reductions and an
+    explicit one."""
+    cfgs = _cfgs_2d() if dim == 2 else _cfgs_3d()
+    for piece, graphs in ((64, True), (128, False)):
+        want = _batch(cfgs, storage, layout=(256, 4))
+        b = _batch(cfgs, storage, layout=(256, 4))
+        b.set_split(piece)
+        pc, active = b.split
+        assert pc == piece and active
+        b.use_graphs(graphs)
+        for x in (b, want):
+            _start(x, cfgs)
+            x.set_reduce_interval(4)
+            x.step(5)
+            x.step(6)
+        for i in range(len(cfgs)):
+            np.testing.assert_array_equal(b.get_populations(i), want.get_populations(i))
+        for x, y in zip(b.last_reduction(), want.last_reduction()):
+            assert x["step"] == y["step"] == 7
+            assert x["mass"] == y["mass"] and x["energy"] == y["energy"] and x["mdot"] == y["mdot"]
+            assert x["residual"] == y["residual"]
+        for x, y in zip(b.reduce(), want.reduce()):
+            assert x["step"] == y["step"] == 11
+            assert x["mass"] == y["mass"] and x["energy"] == y["energy"] and x["residual"] == y["residual"]
+
+
+def test_batch_split_rejects_bad_piece_and_whole_restores():
+    from paper_1209_6548_amd import EsbgkError
+    cfgs = _cfgs_2d()
+    b = _batch(cfgs, "f32")
+    for bad in (-64, 32, 100):
+        with pytest.raises(EsbgkError):
+            b.set_split(bad)
+    b.set_split(4096)              # larger than every problem: nothing is cut
+    assert b.split == (4096, False)
+    b.set_split(0)
+    assert b.split == (0, False)
