@@ -1,7 +1,7 @@
 // C ABI of batched channel problems: validation, workspace layout, binning
-// (longest problem first into the lightest bin), the autotuner that picks the
-// workgroup size and the number of bins by timing the persistent kernel, and
-// the per-problem state I/O.
+// (longest problem, or piece of a cut problem, first into the lightest bin),
+// the autotuner that picks the workgroup size, the number of bins and the
+// piece size by timing the step launches, and the per-problem state I/O.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
