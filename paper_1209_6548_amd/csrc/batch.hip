@@ -84,13 +84,13 @@ __device__ __forceinline__ uint32_t load_bin(BinTable& bt, const uint32_t* __res
   return np;
 }
 
-// Index k of the bin's problem whose slots hold t0 (cum[k] <= t0 < cum[k+1]);
+// Index k of the bin's piece whose slots hold t0 (cum[k] <= t0 < cum[k+1]);
 // t0 is wavefront-uniform, so the search runs on scalars.
 __device__ __forceinline__ uint32_t find_problem(const BinTable& bt, uint32_t np, uint32_t t0) {
   uint32_t k = 0, hi = np;
   while (hi - k > 1) {
     const uint32_t mid = (k + hi) >> 1;
-    if (__builtin_amdgcn_readfirstlane(bt.cum[mid]) <= t0) k = mid;
+    if (uint32_t(__builtin_amdgcn_readfirstlane(bt.cum[mid])) <= t0) k = mid;
     else hi = mid;
   }
   return k;

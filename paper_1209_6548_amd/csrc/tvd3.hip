@@ -67,7 +67,8 @@ constexpr int tvd3_waves() { return sizeof(S) == 8 ? 1 : 4; }
 // FP32 storage: a workgroup barrier (no memory fence) after every 8 pairs
 // keeps the stacked wavefronts, which read each other's populations as z
 // neighbours, within a few pairs of one another (128^3: 1.43 against 1.53 ms;
-// every 4 or 16 pairs: 1.43 / 1.46 ms). FP16 and FP64 ran slower with it.
+// every 4 or 16 pairs: 1.43 ms, every 32: 1.46 ms). FP16 and FP64 ran slower
+// with it.
 template <typename S>
 constexpr int tvd3_pace() { return sizeof(S) == 4 ? 4 : 0; }
 
