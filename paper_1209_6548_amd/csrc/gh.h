@@ -343,4 +343,16 @@ __device__ __forceinline__ void tvd_terms(bool positive, C f2, C fm1, C f0, C fp
   }
 }
 
+// tvd_terms without a branch on the direction, for loops whose velocity is
+// not a compile-time constant: the same differences and limited slopes (the
+// minmod is symmetric and -(x - y) rounds as y - x), chosen by selects.
+template <typename C>
+__device__ __forceinline__ void tvd_terms_sel(bool positive, C f2, C fm1, C f0, C fp1, C& d, C& m) {
+  const C back = f0 - fm1, fwd = fp1 - f0;
+  const C d2 = positive ? fm1 - f2 : f2 - fp1;   // the difference one cell further upwind
+  d = positive ? back : fwd;
+  const C t = minmod(fwd, back) - minmod(d, d2);
+  m = positive ? t : -t;
+}
+
 }  // namespace esbgk

@@ -184,8 +184,15 @@ k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
         const C nu = sg * gc->nu[p][ax];
         const bool pos = nu > C(0);
         C d, m;
-        tvd_terms<C>(pos, widen<C, S>(cur[side][3 * ax + 3]), widen<C, S>(cur[side][3 * ax + 1]), f0,
-                     widen<C, S>(cur[side][3 * ax + 2]), d, m);
+        // FP64: selects instead of a branch on the direction, 3.73 against
+        // 3.95 ms at 128^3; FP32 and FP16 keep the branch (1.43 against 1.98
+        // ms and 1.22 against 1.55 ms with selects)
+        if constexpr (sizeof(C) == 8)
+          tvd_terms_sel<C>(pos, widen<C, S>(cur[side][3 * ax + 3]), widen<C, S>(cur[side][3 * ax + 1]), f0,
+                           widen<C, S>(cur[side][3 * ax + 2]), d, m);
+        else
+          tvd_terms<C>(pos, widen<C, S>(cur[side][3 * ax + 3]), widen<C, S>(cur[side][3 * ax + 1]), f0,
+                       widen<C, S>(cur[side][3 * ax + 2]), d, m);
         t = fmac(nu, d, t);
         t = fmac(gc->nk[p][ax], m, t);
       }
