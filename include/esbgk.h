@@ -309,11 +309,11 @@ int esbgk_batch_get_populations(esbgk_batch* b, int i, double* h);
  * the largest workgroup and one bin per resident workgroup. */
 int esbgk_batch_set_layout(esbgk_batch* b, int threads, int nbins);
 int esbgk_batch_layout(const esbgk_batch* b, int* threads, int* nbins);
-/* Shape of the current layout: the most problems one workgroup owns, and the
- * most cells one thread updates per step (a bin's thread slots, each problem
- * rounded up to 64 cells, over the workgroup size). Either output may be
- * NULL. */
-int esbgk_batch_layout_info(const esbgk_batch* b, int* max_problems_per_bin, int64_t* max_cells_per_thread);
+/* Shape of the current layout: the most pieces (whole problems, or parts of
+ * cut problems) one workgroup owns, and the most cells one thread updates
+ * per step (a bin's thread slots, each piece rounded up to 64 cells, over the
+ * workgroup size). Either output may be NULL. */
+int esbgk_batch_layout_info(const esbgk_batch* b, int* max_pieces_per_bin, int64_t* max_cells_per_thread);
 /* Cut problems larger than piece_cells (a positive multiple of 64; 0 keeps
  * every problem whole, the default) into pieces of that many cells, packed
  * into the bins like problems, so that a batch of few large problems

@@ -728,7 +728,7 @@ int esbgk_batch_last_reduction(esbgk_batch* b, double* out) {
   return fetch_batch_reduction(b, out);
 }
 
-int esbgk_batch_layout_info(const esbgk_batch* b, int* max_problems_per_bin, int64_t* max_cells_per_thread) {
+int esbgk_batch_layout_info(const esbgk_batch* b, int* max_pieces_per_bin, int64_t* max_cells_per_thread) {
   if (!b) return ESBGK_E_INVALID;
   int mp = 0;
   int64_t mc = 0;
@@ -736,7 +736,7 @@ int esbgk_batch_layout_info(const esbgk_batch* b, int* max_problems_per_bin, int
     mp = std::max(mp, int(b->bin_count[k]));
     mc = std::max<int64_t>(mc, (int64_t(b->bin_slots[k]) + b->threads - 1) / b->threads);
   }
-  if (max_problems_per_bin) *max_problems_per_bin = mp;
+  if (max_pieces_per_bin) *max_pieces_per_bin = mp;
   if (max_cells_per_thread) *max_cells_per_thread = mc;
   return ESBGK_OK;
 }
