@@ -78,20 +78,33 @@ k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
        const typename StepT<S>::type* __restrict__ msrc, typename StepT<S>::type* __restrict__ mdst,
        const GH3Consts<typename StepT<S>::type>* __restrict__ gc,
        const LatConsts<typename StepT<S>::type>* __restrict__ lc,
-       const ProbParams<typename StepT<S>::type>* __restrict__ pp) {
+       const ProbParams<typename StepT<S>::type>* __restrict__ pp, uint32_t G) {
   using C = typename StepT<S>::type;
   using L = D3Q216GH;
   constexpr int P = L::P;
   constexpr uint32_t ss = sizeof(S);
   // a workgroup takes one 64-cell chunk of the slice in Z3 = 8 consecutive
-  // slices (one wavefront each), chunks fastest: its wavefronts read each
-  // other's populations as z-neighbours at about the same velocity pair,
-  // and the y-neighbours are chunks started at about the same time (measured
-  // at 128^3 FP32: 2.63 ms against 2.68 for 4 slices and 2.76 for 4 chunks
-  // of one slice)
+  // slices (one wavefront each): its wavefronts read each other's
+  // populations as z-neighbours at about the same velocity pair (measured at
+  // 128^3 FP32: 2.63 ms against 2.68 for 4 slices and 2.76 for 4 chunks of
+  // one slice, in an earlier two-pass build).
+  // Tiles in groups of G consecutive chunks through all bands, band by
+  // band. With more than 8 bands, G = ceil(chunks / 8): each XCD (a
+  // contiguous eighth of the tiles) walks a slab of the slice plane through
+  // the slices, and the resident workgroups of neighbouring slabs move
+  // through the slices together, so the z-neighbours of a band were read
+  // shortly before and the y-neighbours at a slab edge at about the same
+  // time by the next XCD (128^3: FP32 1.38 against 1.43 ms for plain
+  // band-major order, FP64 3.54 against 3.76 ms; same bits). With 8 bands
+  // or fewer, G = all chunks: band-major, each XCD within one band, and
+  // the XCDs of neighbouring bands move through the plane together
+  // (256 x 256 x 64: 2.95 against 3.04 ms for slabs).
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t nchunks = geo.ipad >> 6;
-  const uint32_t band = blk / nchunks, chunk = blk - band * nchunks;
+  const uint32_t nchunks = geo.ipad >> 6, nbands = (geo.nslices + Z3 - 1) / Z3;
+  const uint32_t full = nchunks / G, span = G * nbands, sg = blk / span;
+  const uint32_t g = sg < full ? G : nchunks - full * G;   // the last group may be narrower
+  const uint32_t r = blk - sg * span;
+  const uint32_t band = r / g, chunk = sg * G + (r - band * g);
   const uint32_t i0 = chunk * 64u;
   if (i0 >= geo.inner) return;                       // the slice's padding slots (the whole workgroup)
   // a wavefront beyond the last slice (the last band of a lattice whose
@@ -363,11 +376,14 @@ k_tvd3_moments(Geometry geo, const S* __restrict__ src, const GH3Consts<double>*
 template <typename S>
 static hipError_t tvd3_step_t(const TVDArgs& a) {
   using C = typename StepT<S>::type;
-  const uint32_t nb = (a.geo.ipad >> 6) * ((a.geo.nslices + Z3 - 1) / Z3);
+  const uint32_t nchunks = a.geo.ipad >> 6;
+  const uint32_t nbands = (a.geo.nslices + Z3 - 1) / Z3;
+  const uint32_t nb = nchunks * nbands;
+  const uint32_t G = nbands > 8 ? (nchunks + 7) / 8 : nchunks;   // chunks of a group (nchunks >= 1)
   hipLaunchKernelGGL(k_tvd3<S>, dim3(nb), dim3(STEP3), 0, a.stream, a.geo, static_cast<const S*>(a.src),
                      static_cast<S*>(a.dst), static_cast<const C*>(a.msrc), static_cast<C*>(a.mdst),
                      static_cast<const GH3Consts<C>*>(a.gc), static_cast<const LatConsts<C>*>(a.lc),
-                     static_cast<const ProbParams<C>*>(a.pp));
+                     static_cast<const ProbParams<C>*>(a.pp), G);
   return hipGetLastError();
 }
 

@@ -68,6 +68,22 @@ def test_tvd3_parity(dims, walls, storage):
         assert np.abs(h - ho).max() / np.abs(ho).max() < 1e-12
 
 
+def test_tvd3_slab_order_fp64():
+    # more than 8 bands of 8 slices (65 slices: the last band holds one), so
+    # the tiles go in groups of ceil(9 / 8) = 2 of the slice's 9 chunks (552
+    # cells) through all bands, the last group one chunk wide: every cell is
+    # stepped once, against the oracle population by population
+    dims = (23, 24, 65)
+    lat, prob, f = _pair(dims, "f64", walls=WALLS)
+    steps = 2
+    lat.step(steps)
+    f = OF.run(f, prob, steps)
+    h, ho = lat.get_populations(), f / CUBE.w[:, None] - 1.0
+    assert np.abs(h - ho).max() / np.abs(ho).max() < 1e-12
+    H.assert_parity(lat.read_moments(), _fields(f, prob), "f64")
+    lat.close()
+
+
 def test_tvd3_couette_across_z_fp64():
     # the paper's 1-D setting: walls moving in x, the flow varies along z only
     walls = dict(T=(1.0, 1.0), u=((-0.05, 0.0, 0.0), (0.05, 0.0, 0.0)))
