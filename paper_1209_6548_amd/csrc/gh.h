@@ -312,6 +312,22 @@ __device__ __forceinline__ double minmod(double a, double b) {
   return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
 }
 
+// Value of lane i - 1 (shr) or i + 1 (shl) of the wavefront; the lane
+// whose source is off the wavefront (lane 0, lane 63) keeps its `old`.
+__device__ __forceinline__ int dpp_shift(int old, int v, bool right) {
+  return right ? __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false)    // wave_shr:1
+               : __builtin_amdgcn_update_dpp(old, v, 0x130, 0xf, 0xf, false);   // wave_shl:1
+}
+__device__ __forceinline__ float lane_shift(float old, float v, bool right) {
+  return __builtin_bit_cast(float, dpp_shift(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v), right));
+}
+__device__ __forceinline__ double lane_shift(double old, double v, bool right) {
+  const uint64_t o = __builtin_bit_cast(uint64_t, old), w = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = uint32_t(dpp_shift(int(uint32_t(o)), int(uint32_t(w)), right));
+  const uint32_t hi = uint32_t(dpp_shift(int(uint32_t(o >> 32)), int(uint32_t(w >> 32)), right));
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
 // Cache policy of the TVD kernels' population stores: non-temporal (2) when
 // a cell's Q populations take 144 bytes or more, else the default (0). The
 // stencil re-reads of the neighbouring rows are served by L2, and keeping the

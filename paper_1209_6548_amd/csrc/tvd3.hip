@@ -72,7 +72,7 @@ constexpr int tvd3_waves() { return sizeof(S) == 8 ? 1 : 4; }
 template <typename S>
 constexpr int tvd3_pace() { return sizeof(S) == 4 ? 4 : 0; }
 
-template <typename S>
+template <typename S, bool XD>
 __global__ void __launch_bounds__(STEP3, tvd3_waves<S>())
 k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
        const typename StepT<S>::type* __restrict__ msrc, typename StepT<S>::type* __restrict__ mdst,
@@ -125,6 +125,18 @@ k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
     xo[k + 2] = uint32_t(y * nx + wrapc(x + k, nx)) * ss;
     yo[k + 2] = uint32_t(wrapc(y + k, ny) * nx + x) * ss;
   }
+  // XD (nx a multiple of 64): the chunk lies in one row, and the x
+  // neighbours come from the neighbouring lanes by wavefront shifts; one
+  // halo load per velocity brings x0 - 2, x0 - 1 (lanes 1, 0..31) and
+  // x0 + 64, x0 + 65 (lanes 32..63, 62) of the chunk's row
+  uint32_t hoff = 0;
+  if constexpr (XD) {
+    const int x0 = x - int(lane);
+    int hx = lane < 32u ? wrapc(x0 - 1, nx) : wrapc(x0 + 64, nx);
+    if (lane == 1u) hx = wrapc(x0 - 2, nx);
+    if (lane == 62u) hx = wrapc(x0 + 65, nx);
+    hoff = uint32_t(y * nx + hx) * ss;
+  }
   const uint32_t so = (i0 + lane) * ss;
   const uint32_t bb = geo.sstride * ss, pb = geo.pstride * ss;
   Rsrc row[5];
@@ -164,9 +176,13 @@ k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
       for (int ax = 0; ax < 3; ++ax) {
         const bool pos = sg * gc->nu[p][ax] > C(0);
         if (ax == 0) {
-          v[side][1] = buf_ld<S>(row[2], xo[1], po);
-          v[side][2] = buf_ld<S>(row[2], xo[3], po);
-          v[side][3] = buf_ld<S>(row[2], pos ? xo[0] : xo[4], po);
+          if constexpr (XD) {
+            v[side][1] = buf_ld<S>(row[2], hoff, po);
+          } else {
+            v[side][1] = buf_ld<S>(row[2], xo[1], po);
+            v[side][2] = buf_ld<S>(row[2], xo[3], po);
+            v[side][3] = buf_ld<S>(row[2], pos ? xo[0] : xo[4], po);
+          }
         } else if (ax == 1) {
           v[side][4] = buf_ld<S>(row[2], yo[1], po);
           v[side][5] = buf_ld<S>(row[2], yo[3], po);
@@ -196,16 +212,26 @@ k_tvd3(Geometry geo, const S* __restrict__ src, S* __restrict__ dst,
       for (int ax = 0; ax < 3; ++ax) {
         const C nu = sg * gc->nu[p][ax];
         const bool pos = nu > C(0);
+        C fm1, fp1, f2;
+        if (XD && ax == 0) {
+          const C H = widen<C, S>(cur[side][1]);
+          fm1 = lane_shift(H, f0, true);
+          fp1 = lane_shift(H, f0, false);
+          f2 = pos ? lane_shift(lane_shift(H, H, false), fm1, true)     // lane 0 takes x0 - 2
+                   : lane_shift(lane_shift(H, H, true), fp1, false);    // lane 63 takes x0 + 65
+        } else {
+          fm1 = widen<C, S>(cur[side][3 * ax + 1]);
+          fp1 = widen<C, S>(cur[side][3 * ax + 2]);
+          f2 = widen<C, S>(cur[side][3 * ax + 3]);
+        }
         C d, m;
         // FP64: selects instead of a branch on the direction, 3.73 against
         // 3.95 ms at 128^3; FP32 and FP16 keep the branch (1.43 against 1.98
         // ms and 1.22 against 1.55 ms with selects)
         if constexpr (sizeof(C) == 8)
-          tvd_terms_sel<C>(pos, widen<C, S>(cur[side][3 * ax + 3]), widen<C, S>(cur[side][3 * ax + 1]), f0,
-                           widen<C, S>(cur[side][3 * ax + 2]), d, m);
+          tvd_terms_sel<C>(pos, f2, fm1, f0, fp1, d, m);
         else
-          tvd_terms<C>(pos, widen<C, S>(cur[side][3 * ax + 3]), widen<C, S>(cur[side][3 * ax + 1]), f0,
-                       widen<C, S>(cur[side][3 * ax + 2]), d, m);
+          tvd_terms<C>(pos, f2, fm1, f0, fp1, d, m);
         t = fmac(nu, d, t);
         t = fmac(gc->nk[p][ax], m, t);
       }
@@ -380,7 +406,8 @@ static hipError_t tvd3_step_t(const TVDArgs& a) {
   const uint32_t nbands = (a.geo.nslices + Z3 - 1) / Z3;
   const uint32_t nb = nchunks * nbands;
   const uint32_t G = nbands > 8 ? (nchunks + 7) / 8 : nchunks;   // chunks of a group (nchunks >= 1)
-  hipLaunchKernelGGL(k_tvd3<S>, dim3(nb), dim3(STEP3), 0, a.stream, a.geo, static_cast<const S*>(a.src),
+  auto* kern = a.geo.nx % 64 == 0 ? k_tvd3<S, true> : k_tvd3<S, false>;
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(STEP3), 0, a.stream, a.geo, static_cast<const S*>(a.src),
                      static_cast<S*>(a.dst), static_cast<const C*>(a.msrc), static_cast<C*>(a.mdst),
                      static_cast<const GH3Consts<C>*>(a.gc), static_cast<const LatConsts<C>*>(a.lc),
                      static_cast<const ProbParams<C>*>(a.pp), G);

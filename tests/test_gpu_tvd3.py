@@ -18,8 +18,10 @@ CUBE = OF.ProductSet(6, 3, 4)
 WALLS = dict(T=(0.97, 1.04), u=((-0.04, 0.02, 0.0), (0.05, -0.01, 0.0)))
 
 # (nx, ny, nz): a slice of 48 cells (one wavefront, idle lanes), a ragged
-# slice of 210 cells (4 wavefronts), rows of one cell
-CASES = [(8, 6, 5), (70, 3, 4), (1, 1, 9)]
+# slice of 210 cells (4 wavefronts), rows of one cell; rows of 64 and 128
+# cells (whole wavefronts: the x neighbours by lane shifts, the halo wrapping
+# to the other end of the row)
+CASES = [(8, 6, 5), (70, 3, 4), (1, 1, 9), (64, 5, 4), (128, 2, 3)]
 
 
 def _fields(f, prob):
