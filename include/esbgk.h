@@ -305,8 +305,10 @@ int esbgk_batch_read_moments(esbgk_batch* b, int i, double* h_out, int* F);
 int esbgk_batch_get_populations(esbgk_batch* b, int i, double* h);
 /* Launch layout: workgroup size (multiple of 64, at most 1024 for F32 and
  * F16, 256 for F64 storage) and number of bins (one workgroup each;
- * problems are packed longest first into the lightest bin). The default is
- * the largest workgroup and one bin per resident workgroup. */
+ * problems are packed longest first into the lightest bin; at most one bin
+ * per problem, or per piece of cut problems: esbgk_batch_layout reports the
+ * count in use). The default is the largest workgroup and one bin per
+ * resident workgroup. */
 int esbgk_batch_set_layout(esbgk_batch* b, int threads, int nbins);
 int esbgk_batch_layout(const esbgk_batch* b, int* threads, int* nbins);
 /* Shape of the current layout: the most pieces (whole problems, or parts of
@@ -321,7 +323,9 @@ int esbgk_batch_layout_info(const esbgk_batch* b, int* max_pieces_per_bin, int64
  * workgroups, so each step is then its own launch (followed, on reduction
  * steps, by a kernel that adds every problem's chunk sums in chunk order:
  * the same bits as whole problems), replayed from graphs of up to 32 steps.
- * Rebuilds the bins with the current workgroup size and bin count.
+ * Rebuilds the bins with the current workgroup size and the bin count last
+ * asked for (the default, esbgk_batch_set_layout or the autotuner's choice),
+ * which the number of pieces caps.
  * E_INVALID for another piece_cells. esbgk_batch_split reports the piece
  * size and whether some problem is cut (active = 1). */
 int esbgk_batch_set_split(esbgk_batch* b, int piece_cells);

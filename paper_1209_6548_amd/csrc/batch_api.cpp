@@ -131,6 +131,7 @@ struct esbgk_batch {
   bool state_set = false;
   int64_t steps = 0;
   uint32_t threads = 0, nbins = 0;
+  uint32_t req_bins = 0;       // the bin count last asked for (nbins is that, capped by the piece count)
   uint32_t piece = 0;          // cells per piece of a cut problem (a multiple of 64); 0: whole problems
   bool split = false;          // some problem is cut into several pieces (one step per launch)
   int cus = 0;
@@ -166,6 +167,7 @@ int bfail(esbgk_batch* b, hipError_t e, const char* where) {
 // or not smaller), longest piece first, each into the bin with the fewest
 // slots (a piece's cells rounded up to a multiple of 64).
 int build_bins(esbgk_batch* b, uint32_t nbins) {
+  const uint32_t requested = nbins;
   struct Piece {
     uint32_t id, c0, n;
   };
@@ -225,6 +227,7 @@ int build_bins(esbgk_batch* b, uint32_t nbins) {
   BHIP(b, hipMemcpyAsync(b->at(b->lay.piece_n), ns.data(), ns.size() * 4, hipMemcpyHostToDevice, b->stream), "bins");
   BHIP(b, hipStreamSynchronize(b->stream), "bins");
   b->nbins = nbins;
+  b->req_bins = requested;
   b->split = split;
   return ESBGK_OK;
 }
@@ -548,7 +551,7 @@ int esbgk_batch_set_split(esbgk_batch* b, int piece_cells) {
   drop_batch_graphs(b);
   const uint32_t old = b->piece;
   b->piece = uint32_t(piece_cells);
-  const int rc = build_bins(b, b->nbins);
+  const int rc = build_bins(b, b->req_bins);
   if (rc) b->piece = old;
   return rc;
 }
@@ -609,7 +612,7 @@ int esbgk_batch_autotune(esbgk_batch* b, int steps_per_trial) {
   BHIP(b, hipEventCreate(&e0), "autotune");
   BHIP(b, hipEventCreate(&e1), "autotune");
   float best = 1e30f;
-  uint32_t best_t = b->threads, best_n = b->nbins, best_p = 0;
+  uint32_t best_t = b->threads, best_n = b->req_bins, best_p = 0;
   for (uint32_t pc : piece_c) {
     b->piece = pc;
     for (int t = 256; t <= maxt; t *= 2) {
@@ -627,7 +630,7 @@ int esbgk_batch_autotune(esbgk_batch* b, int steps_per_trial) {
         if (ms < best) {
           best = ms;
           best_t = uint32_t(t);
-          best_n = b->nbins;
+          best_n = nb;
           best_p = pc;
         }
       }

@@ -268,5 +268,8 @@ def test_batch_split_rejects_bad_piece_and_whole_restores():
             b.set_split(bad)
     b.set_split(4096)              # larger than every problem: nothing is cut
     assert b.split == (4096, False)
+    assert b.layout()[1] == len(cfgs)   # the default bin count, capped at one bin per problem
+    b.set_split(64)                # 11 pieces: the cap rises with them
+    assert b.split == (64, True) and b.layout()[1] == 11
     b.set_split(0)
-    assert b.split == (0, False)
+    assert b.split == (0, False) and b.layout()[1] == len(cfgs)
