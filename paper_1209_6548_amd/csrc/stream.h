@@ -105,17 +105,26 @@ __device__ __forceinline__ bool inslice_interior(const CellPos& p, const Geometr
   return ok;
 }
 
-// Ghost value beyond wall `side` for velocity a, from the partial sums of the
-// source column col (Sec. 3.2: rho_W(col) S_alpha(T_w, u_w), deviational).
+// Ghost value beyond wall `side` for velocity a, from the three partial
+// sums q of the source column (Sec. 3.2: rho_W(col) S_alpha(T_w, u_w),
+// deviational).
 template <class L, typename C, typename P>
-__device__ __forceinline__ C wall_ghost(int a, int side, uint32_t col, const Geometry& geo,
-                                        const P* __restrict__ wp, const ProbParams<C>* __restrict__ pp) {
-  const P* q = wp + uint32_t(side) * 3u * geo.ncols + col;
-  const C part = C(q[0]) + C(q[geo.ncols]) + C(q[2u * geo.ncols]);
+__device__ __forceinline__ C wall_ghost_from(int a, int side, const P (&q)[3], const ProbParams<C>* __restrict__ pp) {
+  const C part = C(q[0]) + C(q[1]) + C(q[2]);
   const C drw = (side ? pp->K0[1] : pp->K0[0]) + (side ? pp->invden[1] : pp->invden[0]) * part;
   const C em1 = side ? pp->Em1[1][a] : pp->Em1[0][a];
   const C eh = side ? pp->Ehat[1][a] : pp->Ehat[0][a];
   return em1 + eh * drw;
+}
+
+// The same from the partial sums of source column col in memory
+// (P wp[2 sides][3 layers][ncols], layer 0 next to the wall).
+template <class L, typename C, typename P>
+__device__ __forceinline__ C wall_ghost(int a, int side, uint32_t col, const Geometry& geo,
+                                        const P* __restrict__ wp, const ProbParams<C>* __restrict__ pp) {
+  const P* q = wp + uint32_t(side) * 3u * geo.ncols + col;
+  const P v[3] = {q[0], q[geo.ncols], q[2u * geo.ncols]};
+  return wall_ghost_from<L, C, P>(a, side, v, pp);
 }
 
 // Population alpha pulled from beyond wall `side` (Sec. 3.2, Maxwell's
@@ -181,6 +190,44 @@ __device__ __forceinline__ void buf_st(S v, Rsrc r, uint32_t voff, uint32_t soff
   }
 }
 
+// Within three layers of diffuse walls (slice s wave-uniform): the
+// populations whose source lies beyond a wall become the wall ghosts. Any
+// velocity with a slice component could come from beyond the wall it moves
+// away from; its three partial sums are loaded through a resource that is
+// empty unless it does, so that the loads of every such velocity are in
+// flight together (a branch per velocity would wait for each in turn), and
+// the ghost replaces the pulled value where it applies.
+template <class L, typename C, typename P>
+__device__ __forceinline__ void diffuse_ghosts(C (&h)[L::Q], uint32_t s, const int (&xo)[7], const int (&yo)[7],
+                                               const Geometry& geo, const P* __restrict__ wp,
+                                               const ProbParams<C>* __restrict__ pp) {
+  constexpr int D = L::D, Q = L::Q;
+  constexpr uint32_t ps = sizeof(P);
+  const int ns = int(geo.nslices);
+  P part[Q][3];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
+    if (es == 0) continue;
+    const int s2 = int(s) - es;
+    const bool beyond = es > 0 ? s2 < 0 : s2 >= ns;
+    const uint32_t side = es > 0 ? 0u : 1u;
+    const Rsrc wr = block_rsrc(wp + side * 3u * geo.ncols, beyond ? 3u * geo.ncols * ps : 0u);
+    const uint32_t col = uint32_t(xo[ex + 3] + yo[ey + 3]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) part[a][k] = buf_ld<P>(wr, col * ps, uint32_t(k) * geo.ncols * ps);
+  }
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const int es = ecomp<L>(a, D - 1);
+    if (es == 0) continue;
+    const int s2 = int(s) - es;
+    const bool beyond = es > 0 ? s2 < 0 : s2 >= ns;
+    const C g = wall_ghost_from<L, C, P>(a, es > 0 ? 0 : 1, part[a], pp);
+    h[a] = beyond ? g : h[a];
+  }
+}
+
 // How a wavefront whose lanes share slice s pulls: the seven slices s-3..s+3
 // inside the lattice and every lane far from the in-slice edges (PULL_FAST:
 // one scalar offset per velocity); the seven slices inside but some lane at
@@ -232,7 +279,9 @@ __device__ __forceinline__ void gather_wave(C (&h)[L::Q], const S* __restrict__ 
     }
 #pragma unroll
     for (int a = 0; a < Q; ++a) h[a] = widen<C, S>(raw[a]);
-    if (geo.walls && (s < 3u || s + 3u >= geo.nslices)) {
+    if (geo.walls && (s < 3u || s + 3u >= geo.nslices) && !pp->specular) {
+      diffuse_ghosts<L, C, P>(h, s, xo, yo, geo, wp, pp);
+    } else if (geo.walls && (s < 3u || s + 3u >= geo.nslices)) {
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
         const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
@@ -356,16 +405,9 @@ __device__ __forceinline__ void gather_local(C (&h)[L::Q], const S* buf, const G
 #pragma unroll
   for (int a = 0; a < Q; ++a) h[a] = widen<C, S>(raw[a]);
   if (geo.walls && (s < 3u || s + 3u >= geo.nslices)) {
-    const int ns = int(geo.nslices);
     int xo[7], yo[7];
     inslice_offsets<L>(p, geo, xo, yo);
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
-      const int s2 = int(s) - es;
-      if (s2 >= 0 && s2 < ns) continue;
-      h[a] = wall_ghost<L, C, P>(a, s2 < 0 ? 0 : 1, uint32_t(xo[ex + 3] + yo[ey + 3]), geo, wp, pp);
-    }
+    diffuse_ghosts<L, C, P>(h, s, xo, yo, geo, wp, pp);
   }
 }
 
