@@ -127,6 +127,24 @@ __device__ __forceinline__ C wall_ghost(int a, int side, uint32_t col, const Geo
   return wall_ghost_from<L, C, P>(a, side, v, pp);
 }
 
+// Source columns of the wall ghosts: used[side][cx][cy] when some velocity
+// pulls across wall `side` from the column at in-slice shift (cx - 3, cy - 3)
+// (cy = 3 in 2-D, where the column is the x position). A constexpr variable,
+// so that it is evaluated by the compiler.
+template <class L>
+struct GhostColumns {
+  bool used[2][7][7];
+  constexpr GhostColumns() : used{} {
+    for (int a = 0; a < L::Q; ++a) {
+      const int es = ecomp<L>(a, L::D - 1);
+      if (es == 0) continue;
+      used[es > 0 ? 0 : 1][ecomp<L>(a, 0) + 3][L::D == 3 ? ecomp<L>(a, 1) + 3 : 3] = true;
+    }
+  }
+};
+template <class L>
+inline constexpr GhostColumns<L> ghost_columns{};
+
 // Population alpha pulled from beyond wall `side` (Sec. 3.2, Maxwell's
 // model): gamma times the diffuse ghost plus 1 - gamma times the specular
 // image, velocity mirror(alpha) leaving the mirrored layer of the same source
@@ -438,7 +456,40 @@ __device__ __forceinline__ void gather_lane(C (&h)[L::Q], const S* __restrict__ 
   }
 #pragma unroll
   for (int a = 0; a < Q; ++a) h[a] = widen<C, S>(raw[a]);
-  if (walls && (s < 3 || s + 3 >= ns)) {
+  const bool edge = walls && (s < 3 || s + 3 >= ns);
+  if (D == 2 && walls && !pp->specular && __any(edge)) {
+    // diffuse walls in 2-D: the three partial sums of every source column
+    // that some lane's wall needs are loaded once per wavefront (each lane
+    // at its own column, an address inside the sums), all before any is
+    // used; a branch per velocity and lane would wait for each load in turn
+    // (in 3-D the 18 columns' sums do not fit the registers of a
+    // 1024-thread workgroup, which keeps that loop)
+    int xo[7], yo[7];
+    inslice_offsets<L>(p, geo, xo, yo);
+    const bool near[2] = {__any(walls && s < 3) != 0, __any(walls && s + 3 >= ns) != 0};
+    P raw3[2][7][7][3];
+#pragma unroll
+    for (int side = 0; side < 2; ++side)
+#pragma unroll
+      for (int cx = 0; cx < 7; ++cx)
+#pragma unroll
+        for (int cy = 0; cy < 7; ++cy) {
+          if (!ghost_columns<L>.used[side][cx][cy] || !near[side]) continue;
+          const P* q = wp + uint32_t(side) * 3u * geo.ncols + uint32_t(xo[cx] + yo[cy]);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) raw3[side][cx][cy][k] = q[uint32_t(k) * geo.ncols];
+        }
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
+      if (es == 0) continue;
+      const int side = es > 0 ? 0 : 1, cx = ex + 3, cy = D == 3 ? ey + 3 : 3;
+      if (!near[side]) continue;
+      const bool beyond = edge && (es > 0 ? s - es < 0 : s - es >= ns);
+      const C g = wall_ghost_from<L, C, P>(a, side, raw3[side][cx][cy], pp);
+      h[a] = beyond ? g : h[a];
+    }
+  } else if (edge) {
     int xo[7], yo[7];
     inslice_offsets<L>(p, geo, xo, yo);
 #pragma unroll
