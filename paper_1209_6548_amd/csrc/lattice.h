@@ -64,13 +64,31 @@ __host__ __device__ constexpr int opposite(int alpha) {
 // negated and whose other components are alpha's: the specular image at a
 // wall across the last axis.
 template <class L>
-__host__ __device__ constexpr int mirror(int alpha) {
+__host__ __device__ constexpr int mirror_search(int alpha) {
   for (int b = 0; b < L::Q; ++b) {
     bool same = ecomp<L>(b, L::D - 1) == -ecomp<L>(alpha, L::D - 1);
     for (int k = 0; k < L::D - 1; ++k) same = same && ecomp<L>(b, k) == ecomp<L>(alpha, k);
     if (same) return b;
   }
   return -1;
+}
+
+// The images of all velocities, as a constexpr variable: evaluated by the
+// compiler, so that a kernel indexes a constant table (or, at an unrolled
+// index, uses the constant) instead of running the search.
+template <class L>
+struct MirrorTable {
+  int m[L::Q];
+  constexpr MirrorTable() : m{} {
+    for (int a = 0; a < L::Q; ++a) m[a] = mirror_search<L>(a);
+  }
+};
+template <class L>
+inline constexpr MirrorTable<L> mirror_table{};
+
+template <class L>
+__host__ __device__ constexpr int mirror(int alpha) {
+  return mirror_table<L>.m[alpha];
 }
 
 template <class L>
