@@ -129,16 +129,22 @@ __device__ __forceinline__ C wall_ghost(int a, int side, uint32_t col, const Geo
 
 // Source columns of the wall ghosts: used[side][cx][cy] when some velocity
 // pulls across wall `side` from the column at in-slice shift (cx - 3, cy - 3)
-// (cy = 3 in 2-D, where the column is the x position). A constexpr variable,
-// so that it is evaluated by the compiler.
+// (cy = 3 in 2-D, where the column is the x position), and reach[.] the
+// largest number of layers such a velocity crosses (a cell in layer d of
+// that wall needs the column when reach > d). A constexpr variable, so that
+// it is evaluated by the compiler.
 template <class L>
 struct GhostColumns {
   bool used[2][7][7];
-  constexpr GhostColumns() : used{} {
+  int reach[2][7][7];
+  constexpr GhostColumns() : used{}, reach{} {
     for (int a = 0; a < L::Q; ++a) {
       const int es = ecomp<L>(a, L::D - 1);
       if (es == 0) continue;
-      used[es > 0 ? 0 : 1][ecomp<L>(a, 0) + 3][L::D == 3 ? ecomp<L>(a, 1) + 3 : 3] = true;
+      const int side = es > 0 ? 0 : 1, cx = ecomp<L>(a, 0) + 3, cy = L::D == 3 ? ecomp<L>(a, 1) + 3 : 3;
+      used[side][cx][cy] = true;
+      const int r = es > 0 ? es : -es;
+      if (r > reach[side][cx][cy]) reach[side][cx][cy] = r;
     }
   }
 };
@@ -208,42 +214,51 @@ __device__ __forceinline__ void buf_st(S v, Rsrc r, uint32_t voff, uint32_t soff
   }
 }
 
-// Within three layers of diffuse walls (slice s wave-uniform): the
-// populations whose source lies beyond a wall become the wall ghosts. Any
-// velocity with a slice component could come from beyond the wall it moves
-// away from; its three partial sums are loaded through a resource that is
-// empty unless it does, so that the loads of every such velocity are in
-// flight together (a branch per velocity would wait for each in turn), and
-// the ghost replaces the pulled value where it applies.
+// The wall ghosts of a wavefront's cells in slice s (wave-uniform) next to
+// diffuse wall SIDE: the three partial sums of each source column that the
+// wall's velocities pull across from are loaded through a resource that is
+// empty unless the slice's layer needs that column, so that the loads are
+// in flight together (a branch per velocity would wait for each in turn);
+// the ghosts then replace the pulled values where the source lies beyond.
+template <class L, typename C, typename P, int SIDE>
+__device__ __forceinline__ void side_ghosts(C (&h)[L::Q], uint32_t s, const int (&xo)[7], const int (&yo)[7],
+                                            const Geometry& geo, const P* __restrict__ wp,
+                                            const ProbParams<C>* __restrict__ pp) {
+  constexpr int D = L::D, Q = L::Q;
+  constexpr uint32_t ps = sizeof(P);
+  const int ns = int(geo.nslices);
+  const int depth = SIDE == 0 ? int(s) : ns - 1 - int(s);   // the slice's layer from this wall
+  P part[7][7][3];
+#pragma unroll
+  for (int cx = 0; cx < 7; ++cx)
+#pragma unroll
+    for (int cy = 0; cy < 7; ++cy) {
+      if (!ghost_columns<L>.used[SIDE][cx][cy]) continue;
+      const bool need = ghost_columns<L>.reach[SIDE][cx][cy] > depth;
+      const Rsrc wr = block_rsrc(wp + uint32_t(SIDE) * 3u * geo.ncols, need ? 3u * geo.ncols * ps : 0u);
+      const uint32_t col = uint32_t(xo[cx] + yo[cy]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) part[cx][cy][k] = buf_ld<P>(wr, col * ps, uint32_t(k) * geo.ncols * ps);
+    }
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const int es = ecomp<L>(a, D - 1);
+    if (es == 0 || (es > 0) != (SIDE == 0)) continue;
+    const bool beyond = (es > 0 ? es : -es) > depth;
+    const C g = wall_ghost_from<L, C, P>(a, SIDE, part[ecomp<L>(a, 0) + 3][D == 3 ? ecomp<L>(a, 1) + 3 : 3], pp);
+    h[a] = beyond ? g : h[a];
+  }
+}
+
+// Within three layers of diffuse walls: the populations whose source lies
+// beyond a wall become the wall ghosts (a slice of a lattice thinner than
+// six slices can be within reach of both walls).
 template <class L, typename C, typename P>
 __device__ __forceinline__ void diffuse_ghosts(C (&h)[L::Q], uint32_t s, const int (&xo)[7], const int (&yo)[7],
                                                const Geometry& geo, const P* __restrict__ wp,
                                                const ProbParams<C>* __restrict__ pp) {
-  constexpr int D = L::D, Q = L::Q;
-  constexpr uint32_t ps = sizeof(P);
-  const int ns = int(geo.nslices);
-  P part[Q][3];
-#pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
-    if (es == 0) continue;
-    const int s2 = int(s) - es;
-    const bool beyond = es > 0 ? s2 < 0 : s2 >= ns;
-    const uint32_t side = es > 0 ? 0u : 1u;
-    const Rsrc wr = block_rsrc(wp + side * 3u * geo.ncols, beyond ? 3u * geo.ncols * ps : 0u);
-    const uint32_t col = uint32_t(xo[ex + 3] + yo[ey + 3]);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) part[a][k] = buf_ld<P>(wr, col * ps, uint32_t(k) * geo.ncols * ps);
-  }
-#pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    const int es = ecomp<L>(a, D - 1);
-    if (es == 0) continue;
-    const int s2 = int(s) - es;
-    const bool beyond = es > 0 ? s2 < 0 : s2 >= ns;
-    const C g = wall_ghost_from<L, C, P>(a, es > 0 ? 0 : 1, part[a], pp);
-    h[a] = beyond ? g : h[a];
-  }
+  if (s < 3u) side_ghosts<L, C, P, 0>(h, s, xo, yo, geo, wp, pp);
+  if (s + 3u >= geo.nslices) side_ghosts<L, C, P, 1>(h, s, xo, yo, geo, wp, pp);
 }
 
 // How a wavefront whose lanes share slice s pulls: the seven slices s-3..s+3
