@@ -515,7 +515,10 @@ __device__ __forceinline__ void gather_lane(C (&h)[L::Q], const S* __restrict__ 
       const uint32_t off = uint32_t(xo[ex + 3] + yo[ey + 3]);
       const int m = mirror_layer(s2, ns);
       h[a] = wall_pull<L, C, P>(a, s2 < 0 ? 0 : 1, off, geo, wp, pp, [&]() {
-        const OffT e = OffT(m) * OffT(geo.sstride) + OffT(mirror<L>(a)) * OffT(geo.pstride) + OffT(off);
+        // the image velocity by the run-time search, not the table: with the
+        // table this branch is scheduled as straight-line code that the
+        // 3-D batch kernel (128 registers) spills (28-32 values against 3)
+        const OffT e = OffT(m) * OffT(geo.sstride) + OffT(mirror_search<L>(a)) * OffT(geo.pstride) + OffT(off);
         return widen<C, S>(src[e]);
       });
     }
