@@ -444,6 +444,38 @@ __device__ __forceinline__ void gather_local(C (&h)[L::Q], const S* buf, const G
   }
 }
 
+// The wall ghosts of wall SIDE for lanes at arbitrary cells (slice s per
+// lane): the three partial sums of each source column the wall's velocities
+// pull across from, loaded for every lane (the lane's own column, an address
+// inside the sums) and all before any is used; the ghosts then replace the
+// pulled values of the lanes whose source lies beyond the wall.
+template <class L, typename C, typename P, int SIDE>
+__device__ __forceinline__ void lane_side_ghosts(C (&h)[L::Q], int s, const int (&xo)[7], const int (&yo)[7],
+                                                 const Geometry& geo, const P* __restrict__ wp,
+                                                 const ProbParams<C>* __restrict__ pp) {
+  constexpr int D = L::D, Q = L::Q;
+  const int ns = int(geo.nslices);
+  const int depth = SIDE == 0 ? s : ns - 1 - s;   // the lane's layer from this wall
+  P part[7][7][3];
+#pragma unroll
+  for (int cx = 0; cx < 7; ++cx)
+#pragma unroll
+    for (int cy = 0; cy < 7; ++cy) {
+      if (!ghost_columns<L>.used[SIDE][cx][cy]) continue;
+      const P* q = wp + uint32_t(SIDE) * 3u * geo.ncols + uint32_t(xo[cx] + yo[cy]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) part[cx][cy][k] = q[uint32_t(k) * geo.ncols];
+    }
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const int es = ecomp<L>(a, D - 1);
+    if (es == 0 || (es > 0) != (SIDE == 0)) continue;
+    const bool beyond = (es > 0 ? es : -es) > depth;
+    const C g = wall_ghost_from<L, C, P>(a, SIDE, part[ecomp<L>(a, 0) + 3][D == 3 ? ecomp<L>(a, 1) + 3 : 3], pp);
+    h[a] = beyond ? g : h[a];
+  }
+}
+
 // Pull for a lane at an arbitrary cell (no wavefront structure assumed).
 // OffT is the element-offset type: 32-bit for buffers below 4 GiB. As in the
 // wavefront pulls, all Q loads are issued before any is used (a source
@@ -472,38 +504,16 @@ __device__ __forceinline__ void gather_lane(C (&h)[L::Q], const S* __restrict__ 
 #pragma unroll
   for (int a = 0; a < Q; ++a) h[a] = widen<C, S>(raw[a]);
   const bool edge = walls && (s < 3 || s + 3 >= ns);
-  if (D == 2 && walls && !pp->specular && __any(edge)) {
-    // diffuse walls in 2-D: the three partial sums of every source column
-    // that some lane's wall needs are loaded once per wavefront (each lane
-    // at its own column, an address inside the sums), all before any is
-    // used; a branch per velocity and lane would wait for each load in turn
-    // (in 3-D the 18 columns' sums do not fit the registers of a
-    // 1024-thread workgroup, which keeps that loop)
+  if (walls && !pp->specular && __any(edge)) {
+    // diffuse walls: wall by wall, the three partial sums of every source
+    // column that some lane next to that wall needs are loaded once per
+    // wavefront (each lane at its own column, an address inside the sums),
+    // all before any is used; a branch per velocity and lane would wait for
+    // each load in turn
     int xo[7], yo[7];
     inslice_offsets<L>(p, geo, xo, yo);
-    const bool near[2] = {__any(walls && s < 3) != 0, __any(walls && s + 3 >= ns) != 0};
-    P raw3[2][7][7][3];
-#pragma unroll
-    for (int side = 0; side < 2; ++side)
-#pragma unroll
-      for (int cx = 0; cx < 7; ++cx)
-#pragma unroll
-        for (int cy = 0; cy < 7; ++cy) {
-          if (!ghost_columns<L>.used[side][cx][cy] || !near[side]) continue;
-          const P* q = wp + uint32_t(side) * 3u * geo.ncols + uint32_t(xo[cx] + yo[cy]);
-#pragma unroll
-          for (int k = 0; k < 3; ++k) raw3[side][cx][cy][k] = q[uint32_t(k) * geo.ncols];
-        }
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const int ex = ecomp<L>(a, 0), ey = ecomp<L>(a, 1), es = ecomp<L>(a, D - 1);
-      if (es == 0) continue;
-      const int side = es > 0 ? 0 : 1, cx = ex + 3, cy = D == 3 ? ey + 3 : 3;
-      if (!near[side]) continue;
-      const bool beyond = edge && (es > 0 ? s - es < 0 : s - es >= ns);
-      const C g = wall_ghost_from<L, C, P>(a, side, raw3[side][cx][cy], pp);
-      h[a] = beyond ? g : h[a];
-    }
+    if (__any(s < 3)) lane_side_ghosts<L, C, P, 0>(h, s, xo, yo, geo, wp, pp);
+    if (__any(s + 3 >= ns)) lane_side_ghosts<L, C, P, 1>(h, s, xo, yo, geo, wp, pp);
   } else if (edge) {
     int xo[7], yo[7];
     inslice_offsets<L>(p, geo, xo, yo);
