@@ -90,6 +90,7 @@ struct Mono3Table {
   int deg[GH3_MONO];
   int idx[GH3_MONO][4];
   int mult[GH3_MONO];
+  int zdeg[GH3_MONO];   // the power of c_z
 };
 constexpr Mono3Table make_mono3() {
   Mono3Table t{};
@@ -115,6 +116,7 @@ constexpr Mono3Table make_mono3() {
       }
       t.deg[m] = d;
       t.mult[m] = fact[d] / (fact[cnt[0]] * fact[cnt[1]] * fact[cnt[2]]);
+      t.zdeg[m] = cnt[2];
       ++m;
     }
   }
@@ -128,12 +130,21 @@ static_assert(MONO3.deg[2] == 1 && MONO3.deg[3] == 2 && MONO3.deg[9] == 3 && MON
 // Per-set constants (device memory, built on the host) for the 108
 // representatives: weight, the 34 monomials, Courant numbers nu = c dt/dx
 // per axis and nk = |nu| (1 - |nu|) / 2.
+// The representatives fall into 18 groups of six that share (c_x, c_y)
+// (c_x > 0: 3 values, c_y: 6) and differ in c_z (6 values). For a cell, the
+// collision polynomial of a group is a polynomial in c_z alone, formed once
+// per group.
+constexpr int GH3_GROUPS = 18, GH3_GROUP = 6;
+
 template <typename C>
 struct GH3Consts {
   C w[D3Q216GH::P];
   C mono[D3Q216GH::P][GH3_MONO];
   C nu[D3Q216GH::P][3];
   C nk[D3Q216GH::P][3];
+  int order[D3Q216GH::P];        // the pair visited j-th: group by group
+  C cz[D3Q216GH::P];             // its c_z
+  C gxy[GH3_GROUPS][GH3_MONO];   // c_x^i c_y^j of monomial t for group g
 };
 
 // Running sums of the raw moments sum w h (1, c, cc, ccc) over velocity
@@ -219,6 +230,39 @@ __device__ __forceinline__ void collision_gh3(const Moments3<C>& acc, const LatC
     k.k[t] = mult * v;
   }
   k.omw = C(1) - s.omega;
+}
+
+// The collision polynomial of one group as polynomials in c_z: e (even
+// total degree, powers 0..4) and o (odd total degree, powers 0..3).
+template <typename C>
+struct GH3Group {
+  C e[5], o[4];
+};
+
+template <typename C>
+__device__ __forceinline__ void group_poly(const GH3Collision<C>& k, const C* __restrict__ gxy, GH3Group<C>& g) {
+  g.e[0] = k.K0;
+#pragma unroll
+  for (int n = 1; n < 5; ++n) g.e[n] = C(0);
+#pragma unroll
+  for (int n = 0; n < 4; ++n) g.o[n] = C(0);
+#pragma unroll
+  for (int t = 0; t < GH3_MONO; ++t) {
+    const int z = MONO3.zdeg[t];
+    if (MONO3.deg[t] % 2) g.o[z] = fmac(k.k[t], gxy[t], g.o[z]);
+    else g.e[z] = fmac(k.k[t], gxy[t], g.e[z]);
+  }
+}
+
+// Post-collision values of the pair (c, -c) of a group from their
+// pre-collision values, by Horner in c_z: even part shared, odd part
+// changes sign.
+template <typename C>
+__device__ __forceinline__ void collide_pair_group(const GH3Group<C>& g, C omw, C cz, C hp, C hm, C& outp, C& outm) {
+  const C E = fmac(fmac(fmac(fmac(g.e[4], cz, g.e[3]), cz, g.e[2]), cz, g.e[1]), cz, g.e[0]);
+  const C O = fmac(fmac(fmac(g.o[3], cz, g.o[2]), cz, g.o[1]), cz, g.o[0]);
+  outp = fmac(omw, hp, E + O);
+  outm = fmac(omw, hm, E - O);
 }
 
 // Post-collision values of the pair (p, p + P) from their pre-collision

@@ -66,12 +66,15 @@ struct TLayout {
   size_t pop[2], mom[2], gc, lc, pp, gc64, lc64, pp64, walls, c, staging, total;
 };
 
+bool gh3_groups_ok(const SetTab& t);
+
 bool valid_tvd_shape(const esbgk_shape* s, Geometry* g, std::string* why) {
   auto fail = [&](const char* m) { if (why) *why = m; return false; };
   if (!s) return fail("null shape");
   SetTab t;
   if (!set_tab(s->velset, t))
     return fail("velset must be ESBGK_D2Q16GH, ESBGK_D2Q36GH, ESBGK_D2Q64GH or ESBGK_D3Q216GH");
+  if (t.D == 3 && !gh3_groups_ok(t)) return fail("internal: the D3Q216 representatives do not form 18 groups of six");
   if (s->nx < 1 || s->ny < 1 || s->nz < 1) return fail("extents must be >= 1");
   if (t.D == 2 && s->nz != 1) return fail("a 2-D set needs nz = 1");
   if (s->walls != 0 && s->walls != 1) return fail("walls must be 0 (periodic) or 1 (walls across the last axis)");
@@ -162,6 +165,48 @@ void pack_consts(const SetTab& t, double nu_scale, GH3Consts<C>& d) {
       d.nk[p][i] = C(0.5 * std::fabs(nu) * (1.0 - std::fabs(nu)));
     }
   }
+  // visiting order: the representatives grouped by (c_x, c_y) in order of
+  // first appearance, each group's members in velocity order
+  int j = 0, g = 0;
+  std::vector<bool> taken(size_t(t.P), false);
+  for (int p = 0; p < t.P; ++p) {
+    if (taken[size_t(p)]) continue;
+    const double* cp = t.c + 3 * p;
+    for (int k = 0; k < GH3_MONO; ++k) {
+      double v = 1.0;
+      for (int e = 0; e < MONO3.deg[k]; ++e)
+        if (MONO3.idx[k][e] != 2) v *= cp[MONO3.idx[k][e]];
+      d.gxy[g][k] = C(v);
+    }
+    for (int q = p; q < t.P; ++q) {
+      const double* cq = t.c + 3 * q;
+      if (taken[size_t(q)] || cq[0] != cp[0] || cq[1] != cp[1]) continue;
+      taken[size_t(q)] = true;
+      d.order[j] = q;
+      d.cz[j] = C(cq[2]);
+      ++j;
+    }
+    ++g;
+  }
+}
+
+// Whether the representatives form GH3_GROUPS groups of GH3_GROUP that share
+// (c_x, c_y), which the grouped collision of the 3-D kernel assumes.
+bool gh3_groups_ok(const SetTab& t) {
+  std::vector<bool> taken(size_t(t.P), false);
+  int groups = 0;
+  for (int p = 0; p < t.P; ++p) {
+    if (taken[size_t(p)]) continue;
+    int n = 0;
+    for (int q = p; q < t.P; ++q)
+      if (!taken[size_t(q)] && t.c[3 * q] == t.c[3 * p] && t.c[3 * q + 1] == t.c[3 * p + 1]) {
+        taken[size_t(q)] = true;
+        ++n;
+      }
+    if (n != GH3_GROUP) return false;
+    ++groups;
+  }
+  return groups == GH3_GROUPS;
 }
 
 // Wall tables of Sec. 3.2 (see TVDWalls) from the walls' T and u; the walls
