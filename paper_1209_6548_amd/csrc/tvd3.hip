@@ -74,9 +74,8 @@ constexpr int tvd3_pace() { return sizeof(S) == 4 ? 4 : 0; }
 
 // FP64: the pairs visited group by group, each group's collision polynomial
 // formed once as polynomials in c_z (3.13 against 3.29 ms at 128^3). FP32
-// and FP16 keep the monomial sum per pair in velocity order: grouped, their
-// kernels sit at 120-127 of their 128 registers and ran at 1.86 against
-// 1.33 ms (FP32) and 1.71 against 1.16 ms (FP16).
+// and FP16 keep the monomial sum per pair in velocity order: grouped, they
+// ran at 1.86 against 1.33 ms (FP32) and 1.71 against 1.16 ms (FP16).
 template <typename S>
 constexpr bool tvd3_grouped() { return sizeof(S) == 8; }
 
